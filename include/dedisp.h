@@ -1,0 +1,204 @@
+/*
+ * dedisp.h -- C ABI of the MI355X (gfx950) transient-search hot path.
+ *
+ * The library runs the detection chain of "Spotting Radio Transients with the
+ * help of GPUs" (Barsdell, Bailes, Barnes & Fluke): brute-force incoherent
+ * dedispersion of 2-bit filterbank data over many trial DMs (section 2.2),
+ * boxcar matched filtering through a running sum (section 2.3) and peak
+ * finding by a sigma-cut followed by gathering contiguous samples into events
+ * (section 2.3).  Every step runs in hand-written HIP kernels; the caller owns
+ * all data buffers.
+ *
+ * Conventions for every entry point:
+ *   - Pointers documented as "device" must point to device memory of the
+ *     current HIP device; "host" pointers to ordinary host memory.
+ *   - Calls are asynchronous on `stream` unless documented as synchronising.
+ *   - Arguments are validated synchronously; on any non-OK status no output
+ *     buffer is written (except where a CAPACITY result says otherwise) and
+ *     dedisp_last_error() describes the failure.  No call aborts the process
+ *     and no C++ exception crosses this boundary.
+ *   - A device fault raised by earlier asynchronous work is reported as
+ *     DEDISP_ERR_HIP by the next call that synchronises.
+ */
+#ifndef DEDISP_H
+#define DEDISP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque HIP stream (hipStream_t); NULL is the legacy default stream. */
+typedef struct ihipStream_t* dedisp_stream;
+
+typedef enum {
+    DEDISP_OK = 0,
+    DEDISP_ERR_INVALID_ARG = 1,
+    DEDISP_ERR_TOO_FEW_SAMPLES = 2,
+    DEDISP_ERR_OUT_OF_MEMORY = 3,
+    DEDISP_ERR_CAPACITY = 4,
+    DEDISP_ERR_HIP = 5,
+    DEDISP_ERR_UNSUPPORTED = 6,
+    DEDISP_ERR_BUSY = 7
+} dedisp_status;
+
+typedef enum { DEDISP_OUT_I32 = 0, DEDISP_OUT_U16 = 1 } dedisp_out_type;
+
+/* One detected event (section 2.3: a contiguous above-threshold region of one
+ * boxcar series).  40 bytes. */
+typedef struct {
+    int32_t width_idx; /* index into the widths list                            */
+    int32_t dm_idx;    /* DM trial index                                        */
+    int64_t t_start;   /* first sample of the run (boxcar start index)          */
+    int64_t t_end;     /* last sample of the run, inclusive                     */
+    int64_t t_peak;    /* first sample where the boxcar sum is largest          */
+    int32_t b_peak;    /* boxcar sum at t_peak                                  */
+    float snr;         /* (B - mean) / sigma at t_peak, population sigma        */
+} dedisp_event;
+
+typedef struct dedisp_plan_s* dedisp_plan;
+
+/* ------------------------------------------------------------------------
+ * Plan: the DM delay table (section 2.2).
+ *
+ * delay[d][c] = round(K * DM_d * (f_c^-2 - f_top^-2) / tsamp),
+ *   K = 4.148808e3 s MHz^2 pc^-1 cm^3, f_c = f_top + c*df (MHz), tsamp in s,
+ *   rounding half away from zero on the IEEE-double value evaluated as
+ *   fc = f_top + c*df; a = 1/(fc*fc) - 1/(f_top*f_top); x = ((K*DM)*a)/tsamp.
+ * max_delay = max over the table.
+ *
+ * nchans: number of channels, a multiple of 4, 4 <= nchans <= 21844.
+ * f_top_mhz: frequency of channel 0 (the highest); df_mhz < 0 is the channel
+ *   step; the lowest channel f_top + (nchans-1)*df must be > 0.
+ * tsamp_s > 0: sampling interval.
+ * dm_list: host, ndm finite values >= 0, non-decreasing.  Copied.
+ * plan_out: host, receives the new plan.  The plan owns its device delay table
+ *   and is immutable: it may be used from several streams at once as long as
+ *   every call gets its own workspace.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, HIP (device allocation / copy failed).
+ * ------------------------------------------------------------------------ */
+dedisp_status dedisp_plan_create(int32_t nchans, double f_top_mhz, double df_mhz,
+                                 double tsamp_s, const double* dm_list, int32_t ndm,
+                                 dedisp_plan* plan_out);
+dedisp_status dedisp_plan_destroy(dedisp_plan plan);
+/* Any of the output pointers may be NULL. */
+dedisp_status dedisp_plan_info(dedisp_plan plan, int32_t* nchans, int32_t* ndm,
+                               int64_t* max_delay);
+/* host_out: host, ndm*nchans int32, row-major [d][c]. */
+dedisp_status dedisp_plan_copy_delays(dedisp_plan plan, int32_t* host_out);
+
+/* Bytes of device workspace dedisp_execute needs for nsamps samples (the
+ * channel-major bit-plane copy of the input).  0 on invalid arguments. */
+size_t dedisp_workspace_bytes(dedisp_plan plan, int64_t nsamps);
+
+/* ------------------------------------------------------------------------
+ * Dedispersion (section 2.2): out[d][t] = sum_c in[c][t + delay[d][c]] for
+ * 0 <= t < nout = nsamps - max_delay.  Exact integer result.
+ *
+ * in_2bit: device, nsamps*nchans/4 bytes, time-major: channel c of sample t
+ *   is the unsigned level in bits [2(c%4), 2(c%4)+1] of byte t*nchans/4 + c/4
+ *   (section 1: 2 bits per sample); channel 0 = f_top.
+ * out: device, [ndm][nout] row-major, int32 (DEDISP_OUT_I32) or uint16
+ *   (DEDISP_OUT_U16, exact because 3*nchans <= 65535).
+ * workspace: device, >= dedisp_workspace_bytes(plan, nsamps) bytes, 256-byte
+ *   aligned; clobbered.
+ * Errors: INVALID_ARG (NULL pointers, bad out_type), TOO_FEW_SAMPLES
+ *   (nsamps <= max_delay), HIP (launch failure).  Asynchronous on stream.
+ * ------------------------------------------------------------------------ */
+dedisp_status dedisp_execute(dedisp_plan plan, const uint8_t* in_2bit, int64_t nsamps,
+                             void* out, dedisp_out_type out_type, void* workspace,
+                             dedisp_stream stream);
+
+/* Tile shape of the dedispersion kernel: trials sharing one LDS tile
+ * (4, 8, 16 or 32), 32-sample groups per lane (1 or 2; time tile = 2048 *
+ * groups samples) and channels per LDS stage (multiple of 4, 4..128).  Every
+ * supported shape gives bit-identical output; they differ only in speed. */
+typedef struct {
+    int32_t dms_per_block;
+    int32_t groups;
+    int32_t stage_chans;
+} dedisp_tile;
+
+/* Writes up to `cap` supported shapes to host array `out` (may be NULL when
+ * cap == 0) and returns how many exist. */
+int32_t dedisp_tile_candidates(dedisp_tile* out, int32_t cap);
+
+/* The tile shape dedisp_execute uses for this plan. */
+dedisp_status dedisp_default_tile(dedisp_plan plan, dedisp_tile* out);
+
+/* dedisp_execute with an explicit tile shape (host pointer `tile`).
+ * Errors as dedisp_execute, plus INVALID_ARG for an unsupported shape and
+ * UNSUPPORTED when its LDS tile does not fit for this plan. */
+dedisp_status dedisp_execute_tile(dedisp_plan plan, const uint8_t* in_2bit, int64_t nsamps,
+                                  void* out, dedisp_out_type out_type, void* workspace,
+                                  const dedisp_tile* tile, dedisp_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Boxcar matched filter (section 2.3), materialised for a DM sub-range:
+ *   P[0] = 0, P[t+1] = P[t] + s[t];  B_w[t] = P[t+w] - P[t],
+ *   0 <= t < n_bx = nout - w_max + 1 (leading window; all widths share n_bx).
+ *
+ * in: device [ndm][nout] dedispersed series (int32 or uint16 per in_type).
+ * widths: host, nwidths strictly increasing values >= 1, w_max <= nout,
+ *   nwidths <= 32.
+ * out: device int32 [nwidths][dm_count][n_bx] for DMs [dm_first,
+ *   dm_first+dm_count) of the input.  Every B_w must be < 2^31 (true for
+ *   dedispersed 2-bit data with nchans*3*w_max < 2^31).
+ * Errors: INVALID_ARG, TOO_FEW_SAMPLES (n_bx < 1), HIP.  Asynchronous.
+ * ------------------------------------------------------------------------ */
+dedisp_status boxcar_filter(const void* in, dedisp_out_type in_type, int32_t ndm,
+                            int64_t nout, const int32_t* widths, int32_t nwidths,
+                            int32_t dm_first, int32_t dm_count, int32_t* out,
+                            dedisp_stream stream);
+
+/* Bytes of device workspace find_peaks needs. 0 on invalid arguments. */
+size_t find_peaks_workspace_bytes(int32_t ndm, int64_t nout, const int32_t* widths,
+                                  int32_t nwidths);
+
+/* ------------------------------------------------------------------------
+ * Peak finding (section 2.3): per (width, DM) series of B_w over its n_bx
+ * samples, S1 = sum B, S2 = sum B^2, D = n*S2 - S1^2 (exact integers); a
+ * sample is above the cut when S/N = (n*B - S1)/sqrt(D) > snr_thresh, decided
+ * exactly as B >= ceil((S1 + isqrt(floor(k^2 D)) + 1)/n) with k the float
+ * value of snr_thresh; D == 0 gives no events.  Maximal runs of consecutive
+ * above-cut samples of one series become events, listed in (width_idx,
+ * dm_idx, t_start) order; t_peak is the first maximum of the run and snr is
+ * float((double)(n*B - S1) / sqrt((double)D)) at t_peak.
+ *
+ * in: device [ndm][nout] dedispersed series (int32 or uint16).
+ * widths: host, as for boxcar_filter.  snr_thresh: finite, > 0.
+ * events: device, capacity records.  n_events: host, receives the total
+ *   number found.  If it exceeds capacity the first `capacity` events (in
+ *   order) are written and DEDISP_ERR_CAPACITY is returned.
+ * workspace: device, >= find_peaks_workspace_bytes(...) bytes; clobbered.
+ * Synchronises `stream` (the event count is read back).
+ * Errors: INVALID_ARG, TOO_FEW_SAMPLES, CAPACITY, HIP.
+ * ------------------------------------------------------------------------ */
+dedisp_status find_peaks(const void* in, dedisp_out_type in_type, int32_t ndm,
+                         int64_t nout, const int32_t* widths, int32_t nwidths,
+                         float snr_thresh, dedisp_event* events, int64_t capacity,
+                         int64_t* n_events, void* workspace, dedisp_stream stream);
+
+/* Per-series statistics of the last find_peaks call that used `workspace`
+ * with the same (ndm, nout, widths).  Host outputs of nwidths*ndm entries,
+ * [w][d] order, any may be NULL: s1 = S1; s2_lo/s2_hi = low/high 64 bits of
+ * S2; thr = B_thr, or -1 when D == 0 (no events), or INT64_MAX when no
+ * value can pass.  Synchronises `stream`. */
+dedisp_status find_peaks_read_stats(const void* workspace, int32_t ndm, int64_t nout,
+                                    const int32_t* widths, int32_t nwidths, int64_t* s1,
+                                    uint64_t* s2_lo, uint64_t* s2_hi, int64_t* thr,
+                                    dedisp_stream stream);
+
+/* Thread-local description of the last non-OK status ("" if none). */
+const char* dedisp_last_error(void);
+
+/* Library version string. */
+const char* dedisp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEDISP_H */

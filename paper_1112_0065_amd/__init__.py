@@ -1,0 +1,14 @@
+"""MI355X (gfx950) transient-search hot path.
+
+Brute-force incoherent dedispersion of 2-bit filterbank data, boxcar matched
+filtering and exact sigma-cut peak finding (sections 2.2 and 2.3 of
+"Spotting Radio Transients with the help of GPUs"), as hand-written HIP
+kernels behind the C ABI in include/dedisp.h.  This package is the thin
+Python binding (``_lib``) plus small device-memory helpers (``api``).
+"""
+from ._lib import (  # noqa: F401
+    DedispError, EVENT_DTYPE, OUT_I32, OUT_U16, Plan, boxcar_filter, dedisp_default_tile,
+    dedisp_execute, dedisp_execute_tile, dedisp_last_error, dedisp_plan_copy_delays,
+    dedisp_plan_create, dedisp_plan_info, dedisp_tile_candidates, dedisp_workspace_bytes,
+    events_from_buffer, find_peaks, find_peaks_read_stats, find_peaks_workspace_bytes, lib,
+)

@@ -1,0 +1,274 @@
+"""ctypes binding of libdedisp.so: argument marshalling only.
+
+Function names match the C ABI in include/dedisp.h.  Device buffers are
+passed as torch tensors on the ROCm device (only their data pointers cross
+the boundary) and the stream is torch's current stream unless one is given.
+Every computation happens in the library's HIP kernels; there is no Python
+or CPU fallback: if the library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdedisp.so")
+
+OK, ERR_INVALID_ARG, ERR_TOO_FEW_SAMPLES, ERR_OUT_OF_MEMORY, ERR_CAPACITY, ERR_HIP, \
+    ERR_UNSUPPORTED, ERR_BUSY = range(8)
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "TOO_FEW_SAMPLES", 3: "OUT_OF_MEMORY",
+                4: "CAPACITY", 5: "HIP", 6: "UNSUPPORTED", 7: "BUSY"}
+OUT_I32, OUT_U16 = 0, 1
+
+# dedisp_event, 40 bytes
+EVENT_DTYPE = np.dtype([("width_idx", "<i4"), ("dm_idx", "<i4"), ("t_start", "<i8"),
+                        ("t_end", "<i8"), ("t_peak", "<i8"), ("b_peak", "<i4"),
+                        ("snr", "<f4")])
+assert EVENT_DTYPE.itemsize == 40
+
+
+class DedispError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Tile(C.Structure):
+    _fields_ = [("dms_per_block", C.c_int32), ("groups", C.c_int32), ("stage_chans", C.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libdedisp.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1112_0065_amd.build`")
+    # One HIP runtime per process: torch (which supplies device memory and
+    # streams) must load its libamdhip64 first, so that the library's
+    # dependency on the same soname binds to that copy.
+    import torch  # noqa: F401
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, f64, f32, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_float, C.c_size_t
+    P = C.POINTER
+    sig = {
+        "dedisp_plan_create": (i32, [i32, f64, f64, f64, P(f64), i32, P(vp)]),
+        "dedisp_plan_destroy": (i32, [vp]),
+        "dedisp_plan_info": (i32, [vp, P(i32), P(i32), P(i64)]),
+        "dedisp_plan_copy_delays": (i32, [vp, P(i32)]),
+        "dedisp_workspace_bytes": (sz, [vp, i64]),
+        "dedisp_execute": (i32, [vp, vp, i64, vp, i32, vp, vp]),
+        "dedisp_tile_candidates": (i32, [P(_Tile), i32]),
+        "dedisp_default_tile": (i32, [vp, P(_Tile)]),
+        "dedisp_execute_tile": (i32, [vp, vp, i64, vp, i32, vp, P(_Tile), vp]),
+        "boxcar_filter": (i32, [vp, i32, i32, i64, P(i32), i32, i32, i32, vp, vp]),
+        "find_peaks_workspace_bytes": (sz, [i32, i64, P(i32), i32]),
+        "find_peaks": (i32, [vp, i32, i32, i64, P(i32), i32, f32, vp, i64, P(i64), vp, vp]),
+        "find_peaks_read_stats": (i32, [vp, i32, i64, P(i32), i32, P(i64), P(C.c_uint64),
+                                        P(C.c_uint64), P(i64), vp]),
+        "dedisp_last_error": (C.c_char_p, []),
+        "dedisp_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def declared_symbols() -> list:
+    """Names of every function include/dedisp.h declares."""
+    import re
+    hdr = os.path.join(os.path.dirname(HERE), "include", "dedisp.h")
+    text = open(hdr).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", text)) -
+                  {"if", "sizeof", "defined"})
+
+
+def dedisp_last_error() -> str:
+    return lib().dedisp_last_error().decode()
+
+
+def _check(st: int):
+    if st != OK:
+        raise DedispError(st, dedisp_last_error())
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream) or None
+    if isinstance(stream, int):
+        return stream or None
+    return int(stream.cuda_stream) or None
+
+
+def _i32arr(xs: Sequence[int]):
+    a = (C.c_int32 * len(xs))(*[int(x) for x in xs])
+    return a
+
+
+# ---------------------------------------------------------------------------
+# Plan
+# ---------------------------------------------------------------------------
+
+class Plan:
+    """Owns a dedisp_plan handle."""
+
+    def __init__(self, handle: int, nchans: int, ndm: int, max_delay: int):
+        self.handle = handle
+        self.nchans = nchans
+        self.ndm = ndm
+        self.max_delay = max_delay
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.dedisp_plan_destroy(self.handle)
+            self.handle = None
+
+    @property
+    def _as_parameter_(self):
+        return C.c_void_p(self.handle)
+
+
+def dedisp_plan_create(nchans: int, f_top: float, df: float, tsamp: float, dm_list) -> Plan:
+    dms = np.ascontiguousarray(np.asarray(dm_list, dtype=np.float64))
+    h = C.c_void_p()
+    _check(lib().dedisp_plan_create(int(nchans), float(f_top), float(df), float(tsamp),
+                                    dms.ctypes.data_as(C.POINTER(C.c_double)), len(dms),
+                                    C.byref(h)))
+    nc, nd, md = dedisp_plan_info_raw(h.value)
+    return Plan(h.value, nc, nd, md)
+
+
+def dedisp_plan_info_raw(handle: int):
+    nc, nd, md = C.c_int32(), C.c_int32(), C.c_int64()
+    _check(lib().dedisp_plan_info(handle, C.byref(nc), C.byref(nd), C.byref(md)))
+    return nc.value, nd.value, md.value
+
+
+def dedisp_plan_info(plan: Plan):
+    return dedisp_plan_info_raw(plan.handle)
+
+
+def dedisp_plan_copy_delays(plan: Plan) -> np.ndarray:
+    out = np.empty((plan.ndm, plan.nchans), dtype=np.int32)
+    _check(lib().dedisp_plan_copy_delays(plan.handle, out.ctypes.data_as(C.POINTER(C.c_int32))))
+    return out
+
+
+def dedisp_workspace_bytes(plan: Plan, nsamps: int) -> int:
+    return int(lib().dedisp_workspace_bytes(plan.handle, int(nsamps)))
+
+
+# ---------------------------------------------------------------------------
+# Dedispersion
+# ---------------------------------------------------------------------------
+
+def dedisp_execute(plan: Plan, in_2bit, nsamps: int, out, workspace, stream=None):
+    """in_2bit: uint8 device tensor; out: int32 or uint16 device tensor
+    [ndm][nsamps - max_delay]; workspace: device tensor of
+    dedisp_workspace_bytes(plan, nsamps) bytes."""
+    _check(lib().dedisp_execute(plan.handle, _ptr(in_2bit), int(nsamps), _ptr(out),
+                                _out_type(out), _ptr(workspace), _stream(stream)))
+
+
+def dedisp_tile_candidates():
+    n = lib().dedisp_tile_candidates(None, 0)
+    arr = (_Tile * n)()
+    lib().dedisp_tile_candidates(arr, n)
+    return [(t.dms_per_block, t.groups, t.stage_chans) for t in arr]
+
+
+def dedisp_default_tile(plan: Plan):
+    t = _Tile()
+    _check(lib().dedisp_default_tile(plan.handle, C.byref(t)))
+    return (t.dms_per_block, t.groups, t.stage_chans)
+
+
+def dedisp_execute_tile(plan: Plan, in_2bit, nsamps: int, out, workspace, tile, stream=None):
+    t = _Tile(*[int(v) for v in tile])
+    _check(lib().dedisp_execute_tile(plan.handle, _ptr(in_2bit), int(nsamps), _ptr(out),
+                                     _out_type(out), _ptr(workspace), C.byref(t),
+                                     _stream(stream)))
+
+
+def _out_type(t) -> int:
+    import torch
+    if t.dtype == torch.int32:
+        return OUT_I32
+    if t.dtype in (torch.uint16, torch.int16):
+        return OUT_U16
+    raise TypeError(f"dedispersed series must be int32 or uint16, got {t.dtype}")
+
+
+# ---------------------------------------------------------------------------
+# Boxcar / peaks
+# ---------------------------------------------------------------------------
+
+def boxcar_filter(series, ndm: int, nout: int, widths, dm_first: int, dm_count: int, out,
+                  stream=None):
+    w = _i32arr(widths)
+    _check(lib().boxcar_filter(_ptr(series), _out_type(series), int(ndm), int(nout), w,
+                               len(widths), int(dm_first), int(dm_count), _ptr(out),
+                               _stream(stream)))
+
+
+def find_peaks_workspace_bytes(ndm: int, nout: int, widths) -> int:
+    return int(lib().find_peaks_workspace_bytes(int(ndm), int(nout), _i32arr(widths),
+                                                len(widths)))
+
+
+def find_peaks(series, ndm: int, nout: int, widths, snr_thresh: float, events, capacity: int,
+               workspace, stream=None) -> int:
+    """events: device buffer of capacity*40 bytes.  Returns the number of
+    events found (raises DedispError(CAPACITY) when it exceeds capacity,
+    after writing the first `capacity`)."""
+    n = C.c_int64()
+    st = lib().find_peaks(_ptr(series), _out_type(series), int(ndm), int(nout),
+                          _i32arr(widths), len(widths), float(snr_thresh), _ptr(events),
+                          int(capacity), C.byref(n), _ptr(workspace), _stream(stream))
+    if st == ERR_CAPACITY:
+        raise DedispError(st, dedisp_last_error() + f" (n_events={n.value})")
+    _check(st)
+    return int(n.value)
+
+
+def find_peaks_read_stats(workspace, ndm: int, nout: int, widths, stream=None):
+    """(s1, s2, thr) as [nwidths][ndm] arrays (s2 as Python ints, exact)."""
+    nw = len(widths)
+    s1 = np.empty(nw * ndm, np.int64)
+    lo = np.empty(nw * ndm, np.uint64)
+    hi = np.empty(nw * ndm, np.uint64)
+    thr = np.empty(nw * ndm, np.int64)
+    _check(lib().find_peaks_read_stats(
+        _ptr(workspace), int(ndm), int(nout), _i32arr(widths), nw,
+        s1.ctypes.data_as(C.POINTER(C.c_int64)), lo.ctypes.data_as(C.POINTER(C.c_uint64)),
+        hi.ctypes.data_as(C.POINTER(C.c_uint64)), thr.ctypes.data_as(C.POINTER(C.c_int64)),
+        _stream(stream)))
+    s2 = np.array([int(h) << 64 | int(l) for h, l in zip(hi.tolist(), lo.tolist())],
+                  dtype=object)
+    return s1.reshape(nw, ndm), s2.reshape(nw, ndm), thr.reshape(nw, ndm)
+
+
+def events_from_buffer(buf, n: int) -> np.ndarray:
+    """Copy n event records from a device/host byte buffer to a structured array."""
+    raw = buf[: n * EVENT_DTYPE.itemsize]
+    if hasattr(raw, "cpu"):
+        raw = raw.cpu().numpy()
+    return np.frombuffer(np.asarray(raw, dtype=np.uint8).tobytes(), dtype=EVENT_DTYPE, count=n)

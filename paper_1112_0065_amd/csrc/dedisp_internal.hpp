@@ -1,0 +1,78 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dedisp.h"
+
+namespace dd {
+
+// Record the message for dedisp_last_error() and return the status.
+dedisp_status fail(dedisp_status st, const char* fmt, ...);
+void clear_error();
+
+#define DD_HIP(expr)                                                          \
+    do {                                                                      \
+        hipError_t e_ = (expr);                                               \
+        if (e_ != hipSuccess)                                                 \
+            return ::dd::fail(DEDISP_ERR_HIP, "%s failed: %s", #expr,         \
+                              hipGetErrorString(e_));                         \
+    } while (0)
+
+// Number of bit-slice levels the accumulator needs for sums <= 3*nchans.
+inline int levels_for(int nchans) { return 3 * nchans <= 4095 ? 12 : 16; }
+
+// Tile shapes of the dedispersion kernel.
+struct TileConfig {
+    int dms_per_block;   // DM trials sharing one LDS tile (multiple of the waves)
+    int groups;          // 32-sample groups per lane (time tile = 2048*groups)
+    int stage_chans;     // channels per LDS stage (multiple of 4)
+};
+
+// Words (uint2 = one 32-sample lo/hi bit-plane pair) per channel in the
+// channel-major copy of the input.
+inline int64_t repack_words(int64_t nsamps) { return 2 * ((nsamps + 63) / 64) + 2; }
+
+}  // namespace dd
+
+struct dedisp_plan_s {
+    int32_t nchans = 0;
+    int32_t ndm = 0;
+    double f_top = 0, df = 0, tsamp = 0;
+    std::vector<double> dm_list;
+    std::vector<int32_t> delays;      // host copy [ndm][nchans]
+    int64_t max_delay = 0;
+    int32_t* d_delays = nullptr;      // device copy [ndm][nchans]
+    int device = 0;
+    // Per DM-block skew (in 32-sample words) for each supported block size.
+    static constexpr int kNumDmBlock = 4;          // 4, 8, 16, 32 DMs
+    int32_t* d_skew[kNumDmBlock] = {nullptr, nullptr, nullptr, nullptr};
+    int32_t skew_max[kNumDmBlock] = {0, 0, 0, 0};
+};
+
+namespace dd {
+
+inline int dm_block_index(int dms_per_block) {
+    switch (dms_per_block) {
+        case 4: return 0;
+        case 8: return 1;
+        case 16: return 2;
+        case 32: return 3;
+        default: return -1;
+    }
+}
+
+// Kernel launchers (asynchronous; return hipError_t of the launch).
+hipError_t launch_repack(const uint8_t* in, int64_t nsamps, int nchans, uint2* words,
+                         int64_t nwords, hipStream_t s);
+dedisp_status launch_dedisperse(const dedisp_plan_s* p, const uint2* words,
+                                int64_t nwords, int64_t nout, void* out, int out_u16,
+                                const TileConfig& cfg, hipStream_t s);
+TileConfig default_tile_config(const dedisp_plan_s* p);
+
+}  // namespace dd

@@ -1,0 +1,648 @@
+// Boxcar matched filter, exact sigma-cut and peak finding (paper section 2.3).
+//
+// Boxcars come from a running sum: B_w[t] = P[t+w] - P[t] with P the prefix
+// sum of a dedispersed series (the leading window; every width shares the
+// valid length n_bx = nout - w_max + 1).  A block owns one (DM, segment of
+// L start positions); it scans its window of the series in LDS with a
+// wave-shuffle prefix sum -- only differences of P are used, so a segment
+// needs no carry from the segments before it -- and evaluates every width
+// from that one scan.  All boxcar arithmetic is uint32 modular (exact, since
+// each B_w < 2^31).
+//
+// The sigma-cut is decided in integers: per (width, DM) series the exact sums
+// S1 = sum B and S2 = sum B^2 give D = n S2 - S1^2, and a sample is above the
+// cut iff B >= B_thr = ceil((S1 + isqrt(floor(k^2 D)) + 1) / n), k being the
+// exact binary value of the float threshold (128/256-bit integer helpers).
+//
+// Events (maximal runs of above-cut samples of one series, section 2.3's
+// "contiguous regions gathered into individual events") are compacted
+// deterministically: count run starts per (width, DM, segment), exclusive
+// scan, then write each event at its offset -- the output order is (width,
+// DM, t_start) without any sort.
+#include <cmath>
+
+#include "dedisp_internal.hpp"
+#include "search_internal.hpp"
+
+namespace {
+
+constexpr int kThreads = 256;
+using u128 = unsigned __int128;
+
+struct u256 {
+    uint64_t w[4];
+};
+
+__device__ __forceinline__ u256 u256_from(u128 x) {
+    return u256{{static_cast<uint64_t>(x), static_cast<uint64_t>(x >> 64), 0, 0}};
+}
+
+// a * b for a < 2^128, b < 2^64.
+__device__ __forceinline__ u256 u256_mul_u64(u128 a, uint64_t b) {
+    const uint64_t a0 = static_cast<uint64_t>(a), a1 = static_cast<uint64_t>(a >> 64);
+    const u128 p0 = static_cast<u128>(a0) * b;
+    const u128 p1 = static_cast<u128>(a1) * b + (p0 >> 64);
+    return u256{{static_cast<uint64_t>(p0), static_cast<uint64_t>(p1), static_cast<uint64_t>(p1 >> 64), 0}};
+}
+
+__device__ __forceinline__ u256 u256_shr(u256 a, int s) {
+    u256 r{{0, 0, 0, 0}};
+    const int q = s >> 6, b = s & 63;
+    for (int i = 0; i < 4; ++i) {
+        const int j = i + q;
+        if (j < 4) {
+            uint64_t v = a.w[j] >> b;
+            if (b && j + 1 < 4) v |= a.w[j + 1] << (64 - b);
+            r.w[i] = v;
+        }
+    }
+    return r;
+}
+
+__device__ __forceinline__ u256 u256_shl(u256 a, int s) {
+    u256 r{{0, 0, 0, 0}};
+    const int q = s >> 6, b = s & 63;
+    for (int i = 3; i >= 0; --i) {
+        const int j = i - q;
+        if (j >= 0) {
+            uint64_t v = a.w[j] << b;
+            if (b && j - 1 >= 0) v |= a.w[j - 1] >> (64 - b);
+            r.w[i] = v;
+        }
+    }
+    return r;
+}
+
+__device__ __forceinline__ bool u256_ge(const u256& a, const u256& b) {
+    for (int i = 3; i >= 0; --i)
+        if (a.w[i] != b.w[i]) return a.w[i] > b.w[i];
+    return true;
+}
+
+__device__ __forceinline__ u256 u256_sub(u256 a, const u256& b) {
+    uint64_t borrow = 0;
+    for (int i = 0; i < 4; ++i) {
+        const uint64_t x = a.w[i], y = b.w[i];
+        const uint64_t d = x - y - borrow;
+        borrow = (x < y) || (x - y < borrow) ? 1 : 0;
+        a.w[i] = d;
+    }
+    return a;
+}
+
+__device__ __forceinline__ u256 u256_add(u256 a, const u256& b) {
+    uint64_t carry = 0;
+    for (int i = 0; i < 4; ++i) {
+        const uint64_t s = a.w[i] + b.w[i];
+        const uint64_t c1 = s < a.w[i];
+        const uint64_t s2 = s + carry;
+        const uint64_t c2 = s2 < s;
+        a.w[i] = s2;
+        carry = c1 | c2;
+    }
+    return a;
+}
+
+// floor(sqrt(x)), digit-by-digit (binary restoring method).
+__device__ u256 u256_isqrt(u256 x) {
+    u256 res{{0, 0, 0, 0}};
+    u256 bit{{0, 0, 0, 0}};
+    // highest power of four <= x
+    int top = -1;
+    for (int i = 3; i >= 0 && top < 0; --i)
+        if (x.w[i]) top = 64 * i + 63 - __builtin_clzll(x.w[i]);
+    if (top < 0) return res;
+    const int p = top & ~1;
+    bit.w[p >> 6] = uint64_t(1) << (p & 63);
+    while (bit.w[0] | bit.w[1] | bit.w[2] | bit.w[3]) {
+        const u256 t = u256_add(res, bit);
+        if (u256_ge(x, t)) {
+            x = u256_sub(x, t);
+            res = u256_add(u256_shr(res, 1), bit);
+        } else {
+            res = u256_shr(res, 1);
+        }
+        bit = u256_shr(bit, 2);
+    }
+    return res;
+}
+
+// floor(a / b), a < 2^128, b >= 1 (shift-subtract).
+__device__ u128 u128_div_u64(u128 a, uint64_t b) {
+    u128 q = 0, r = 0;
+    for (int i = 127; i >= 0; --i) {
+        r = (r << 1) | ((a >> i) & 1);
+        if (r >= b) {
+            r -= b;
+            q |= static_cast<u128>(1) << i;
+        }
+    }
+    return q;
+}
+
+// Round-to-nearest-even conversion of an unsigned 128-bit integer.
+__device__ double u128_to_double(u128 x) {
+    if ((x >> 64) == 0) return static_cast<double>(static_cast<uint64_t>(x));
+    const uint64_t hi = static_cast<uint64_t>(x >> 64);
+    const int lz = __builtin_clzll(hi);
+    const int nbits = 128 - lz;          // 65..128
+    const int drop = nbits - 53;
+    u128 m = x >> drop;                  // 53 significant bits
+    const u128 rem = x - (m << drop);
+    const u128 half = static_cast<u128>(1) << (drop - 1);
+    if (rem > half || (rem == half && (m & 1))) m += 1;
+    return ldexp(static_cast<double>(static_cast<uint64_t>(m)), drop);
+}
+
+// ----------------------------------------------------------------------------
+// Block-level helpers.
+// ----------------------------------------------------------------------------
+
+// Exclusive prefix of one value per thread over the block (uint32, modular).
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* wave_tot) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wave_tot[wave] = x;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int i = 0; i < wave; ++i) base += wave_tot[i];
+    __syncthreads();
+    return base + x - v;
+}
+
+// Fill pl[0..n) with the running sum of the series values s[first + i]
+// (values outside [0, nout) count as 0): pl[i] = sum_{k<i} s[first+k].
+template <typename T>
+__device__ void load_prefix(const T* __restrict__ row, int64_t nout, int64_t first, int n,
+                            uint32_t* pl, uint32_t* wave_tot) {
+    // coalesced load of the raw values into pl[1..n)
+    for (int i = threadIdx.x; i < n - 1; i += kThreads) {
+        const int64_t t = first + i;
+        pl[i + 1] = (t >= 0 && t < nout) ? static_cast<uint32_t>(row[t]) : 0u;
+    }
+    __syncthreads();
+    // each thread scans a contiguous chunk (odd chunk stride: no bank conflicts)
+    const int chunk = ((n - 1) + kThreads - 1) / kThreads;
+    const int lo = 1 + threadIdx.x * chunk;
+    const int hi = min(n, lo + chunk);
+    uint32_t sum = 0;
+    for (int i = lo; i < hi; ++i) sum += pl[i];
+    const uint32_t base = block_exclusive_scan(sum, wave_tot);
+    uint32_t run = base;
+    for (int i = lo; i < hi; ++i) {
+        run += pl[i];
+        pl[i] = run;
+    }
+    if (threadIdx.x == 0) pl[0] = 0u;
+    __syncthreads();
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ----------------------------------------------------------------------------
+// Kernels.
+// ----------------------------------------------------------------------------
+
+// Materialised boxcars for a DM sub-range (tests and inspection).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void boxcar_kernel(const T* __restrict__ in, int64_t nout,
+                                                          int64_t nbx, dd::Widths W, int dm_first,
+                                                          int L, int32_t* __restrict__ out,
+                                                          int dm_count) {
+    extern __shared__ uint32_t pl[];
+    __shared__ uint32_t wave_tot[kThreads / 64];
+    const int d = dm_first + blockIdx.y;
+    const int64_t s0 = static_cast<int64_t>(blockIdx.x) * L;
+    const int n = L + W.w[W.n - 1] + 1;
+    load_prefix(in + static_cast<int64_t>(d) * nout, nout, s0 - 1, n, pl, wave_tot);
+    for (int i = threadIdx.x; i < L; i += kThreads) {
+        const int64_t t = s0 + i;
+        if (t >= nbx) break;
+        const uint32_t p0 = pl[i + 1];
+        for (int wi = 0; wi < W.n; ++wi)
+            out[(static_cast<int64_t>(wi) * dm_count + blockIdx.y) * nbx + t] =
+                static_cast<int32_t>(pl[i + 1 + W.w[wi]] - p0);
+    }
+}
+
+// Pass 1: per (width, DM, segment) partial sums of B and B^2.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void boxcar_stats_kernel(const T* __restrict__ in,
+                                                                int64_t nout, int64_t nbx,
+                                                                dd::Widths W, int L, int nseg,
+                                                                dd::PeaksWs ws) {
+    extern __shared__ uint32_t pl[];
+    __shared__ uint32_t wave_tot[kThreads / 64];
+    __shared__ uint64_t red[3][kThreads / 64][dd::kMaxWidths];
+    const int d = blockIdx.y;
+    const int seg = blockIdx.x;
+    const int64_t s0 = static_cast<int64_t>(seg) * L;
+    const int n = L + W.w[W.n - 1] + 1;
+    load_prefix(in + static_cast<int64_t>(d) * nout, nout, s0 - 1, n, pl, wave_tot);
+    const int npos = static_cast<int>(min<int64_t>(L, nbx - s0));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int wi = 0; wi < W.n; ++wi) {
+        const int w = W.w[wi];
+        uint64_t s1 = 0, s2lo = 0, s2hi = 0;
+        for (int i = threadIdx.x; i < npos; i += kThreads) {
+            const uint32_t b = pl[i + 1 + w] - pl[i + 1];
+            s1 += b;
+            const uint64_t sq = static_cast<uint64_t>(b) * b;
+            s2lo += sq;
+            s2hi += (s2lo < sq) ? 1u : 0u;
+        }
+        // s2 = s2hi:s2lo; reduce lo with carries folded into hi.
+        s1 = wave_sum_u64(s1);
+        const uint64_t lo_lo = wave_sum_u64(s2lo & 0xFFFFFFFFull);
+        const uint64_t lo_hi = wave_sum_u64(s2lo >> 32);
+        s2hi = wave_sum_u64(s2hi);
+        if (lane == 0) {
+            const u128 tot = static_cast<u128>(lo_lo) + (static_cast<u128>(lo_hi) << 32) +
+                             (static_cast<u128>(s2hi) << 64);
+            red[0][wave][wi] = s1;
+            red[1][wave][wi] = static_cast<uint64_t>(tot);
+            red[2][wave][wi] = static_cast<uint64_t>(tot >> 64);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < W.n) {
+        const int wi = threadIdx.x;
+        uint64_t s1 = 0;
+        u128 s2 = 0;
+        for (int v = 0; v < kThreads / 64; ++v) {
+            s1 += red[0][v][wi];
+            s2 += static_cast<u128>(red[1][v][wi]) | (static_cast<u128>(red[2][v][wi]) << 64);
+        }
+        const int64_t idx = (static_cast<int64_t>(wi) * gridDim.y + d) * nseg + seg;
+        ws.part_s1[idx] = s1;
+        ws.part_s2lo[idx] = static_cast<uint64_t>(s2);
+        ws.part_s2hi[idx] = static_cast<uint64_t>(s2 >> 64);
+    }
+}
+
+// Pass 2: one thread per (width, DM) series: exact sums, D and B_thr.
+__global__ __launch_bounds__(kThreads) void series_threshold_kernel(int nseries, int nseg,
+                                                                    int64_t nbx, uint32_t kmant,
+                                                                    int kexp2, dd::PeaksWs ws) {
+    const int s = blockIdx.x * kThreads + threadIdx.x;
+    if (s >= nseries) return;
+    uint64_t s1 = 0;
+    u128 s2 = 0;
+    for (int g = 0; g < nseg; ++g) {
+        const int64_t idx = static_cast<int64_t>(s) * nseg + g;
+        s1 += ws.part_s1[idx];
+        s2 += static_cast<u128>(ws.part_s2lo[idx]) | (static_cast<u128>(ws.part_s2hi[idx]) << 64);
+    }
+    const uint64_t n = static_cast<uint64_t>(nbx);
+    const u128 d = static_cast<u128>(n) * s2 - static_cast<u128>(s1) * s1;
+    ws.s1[s] = s1;
+    ws.s2lo[s] = static_cast<uint64_t>(s2);
+    ws.s2hi[s] = static_cast<uint64_t>(s2 >> 64);
+    if (d == 0) {
+        ws.thr[s] = -1;
+        ws.thr32[s] = 0xFFFFFFFFu;
+        ws.sqrt_d[s] = 0.0;
+        return;
+    }
+    // floor(k^2 D) with k = kmant * 2^kexp2 (kexp2 <= 0): (kmant^2 D) >> -2 kexp2
+    const u256 kd = u256_mul_u64(d, static_cast<uint64_t>(kmant) * kmant);
+    const u256 q = kexp2 >= 0 ? u256_shl(kd, 2 * kexp2) : u256_shr(kd, -2 * kexp2);
+    const u256 r = u256_isqrt(q);
+    // lmin = isqrt + 1 < 2^128 here; B_thr = ceil((S1 + lmin) / n)
+    const u128 lmin = (static_cast<u128>(r.w[1]) << 64 | r.w[0]) + 1;
+    int64_t thr;
+    if (r.w[2] | r.w[3] | (r.w[1] >> 62)) {
+        thr = INT64_MAX;
+    } else {
+        const u128 num = static_cast<u128>(s1) + lmin;
+        const u128 b = u128_div_u64(num + (n - 1), n);
+        thr = (b >> 62) ? INT64_MAX : static_cast<int64_t>(b);
+    }
+    ws.thr[s] = thr;
+    ws.thr32[s] = thr > 0xFFFFFFFFll ? 0xFFFFFFFFu : static_cast<uint32_t>(thr);
+    ws.sqrt_d[s] = sqrt(u128_to_double(d));
+}
+
+// Pass 3: number of run starts per (width, DM, segment).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void peaks_count_kernel(const T* __restrict__ in,
+                                                               int64_t nout, int64_t nbx,
+                                                               dd::Widths W, int L, int nseg,
+                                                               dd::PeaksWs ws) {
+    extern __shared__ uint32_t pl[];
+    __shared__ uint32_t wave_tot[kThreads / 64];
+    __shared__ uint32_t cnt[dd::kMaxWidths];
+    const int d = blockIdx.y;
+    const int seg = blockIdx.x;
+    const int ndm = gridDim.y;
+    // Skip the scan when no series of this DM can have events.
+    bool any = false;
+    for (int wi = 0; wi < W.n; ++wi) any |= ws.thr32[wi * ndm + d] != 0xFFFFFFFFu;
+    if (!any) {
+        if (threadIdx.x < W.n)
+            ws.counts[(static_cast<int64_t>(threadIdx.x) * ndm + d) * nseg + seg] = 0;
+        return;
+    }
+    const int64_t s0 = static_cast<int64_t>(seg) * L;
+    const int n = L + W.w[W.n - 1] + 1;
+    if (threadIdx.x < dd::kMaxWidths) cnt[threadIdx.x] = 0;
+    load_prefix(in + static_cast<int64_t>(d) * nout, nout, s0 - 1, n, pl, wave_tot);
+    const int npos = static_cast<int>(min<int64_t>(L, nbx - s0));
+    const int lane = threadIdx.x & 63;
+    for (int wi = 0; wi < W.n; ++wi) {
+        const uint32_t thr = ws.thr32[wi * ndm + d];
+        if (thr == 0xFFFFFFFFu) continue;
+        const int w = W.w[wi];
+        uint32_t c = 0;
+        for (int i = threadIdx.x; i < npos; i += kThreads) {
+            const bool above = pl[i + 1 + w] - pl[i + 1] >= thr;
+            const bool prev = (s0 + i > 0) && (pl[i + w] - pl[i] >= thr);
+            c += (above && !prev) ? 1u : 0u;
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+        if (lane == 0 && c) atomicAdd(&cnt[wi], c);
+    }
+    __syncthreads();
+    if (threadIdx.x < W.n)
+        ws.counts[(static_cast<int64_t>(threadIdx.x) * ndm + d) * nseg + seg] = cnt[threadIdx.x];
+}
+
+// Exclusive scan of counts (uint32) into offsets (int64): three small kernels.
+constexpr int kScanChunk = 4096;
+
+__global__ __launch_bounds__(kThreads) void scan_chunks_kernel(const uint32_t* __restrict__ counts,
+                                                               int64_t n, int64_t* __restrict__ offs,
+                                                               int64_t* __restrict__ chunk_tot) {
+    __shared__ uint32_t wave_tot[kThreads / 64];
+    __shared__ int64_t carry;
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kScanChunk;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < kScanChunk; base += kThreads) {
+        const int64_t i = c0 + base + threadIdx.x;
+        const uint32_t v = i < n ? counts[i] : 0u;
+        const uint32_t ex = block_exclusive_scan(v, wave_tot);
+        const int64_t cur = carry;
+        if (i < n) offs[i] = cur + ex;
+        __syncthreads();
+        if (threadIdx.x == kThreads - 1) carry = cur + ex + v;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) chunk_tot[blockIdx.x] = carry;
+}
+
+__global__ void scan_totals_kernel(int64_t* __restrict__ chunk_tot, int nchunks,
+                                   int64_t* __restrict__ total) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t run = 0;
+    for (int i = 0; i < nchunks; ++i) {
+        const int64_t v = chunk_tot[i];
+        chunk_tot[i] = run;
+        run += v;
+    }
+    *total = run;
+}
+
+__global__ __launch_bounds__(kThreads) void scan_add_kernel(int64_t* __restrict__ offs, int64_t n,
+                                                            const int64_t* __restrict__ chunk_tot) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < n) offs[i] += chunk_tot[i / kScanChunk];
+}
+
+// Pass 4: write the events of segments that have any.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void peaks_write_kernel(const T* __restrict__ in,
+                                                               int64_t nout, int64_t nbx,
+                                                               dd::Widths W, int L, int nseg,
+                                                               dd::PeaksWs ws,
+                                                               dedisp_event* __restrict__ events,
+                                                               int64_t capacity) {
+    extern __shared__ uint32_t pl[];
+    __shared__ uint32_t wave_tot[kThreads / 64];
+    const int d = blockIdx.y;
+    const int seg = blockIdx.x;
+    const int ndm = gridDim.y;
+    bool any = false;
+    for (int wi = 0; wi < W.n; ++wi)
+        any |= ws.counts[(static_cast<int64_t>(wi) * ndm + d) * nseg + seg] != 0;
+    if (!any) return;
+    const int64_t s0 = static_cast<int64_t>(seg) * L;
+    const int n = L + W.w[W.n - 1] + 1;
+    const T* row = in + static_cast<int64_t>(d) * nout;
+    load_prefix(row, nout, s0 - 1, n, pl, wave_tot);
+    const int npos = static_cast<int>(min<int64_t>(L, nbx - s0));
+    for (int wi = 0; wi < W.n; ++wi) {
+        const int64_t cidx = (static_cast<int64_t>(wi) * ndm + d) * nseg + seg;
+        if (ws.counts[cidx] == 0) continue;
+        const int sidx = wi * ndm + d;
+        const uint32_t thr = ws.thr32[sidx];
+        const int w = W.w[wi];
+        int64_t rank = ws.offs[cidx];
+        for (int base = 0; base < npos; base += kThreads) {
+            const int i = base + threadIdx.x;
+            bool start = false;
+            uint32_t b = 0;
+            if (i < npos) {
+                b = pl[i + 1 + w] - pl[i + 1];
+                const bool prev = (s0 + i > 0) && (pl[i + w] - pl[i] >= thr);
+                start = b >= thr && !prev;
+            }
+            const uint32_t ex = block_exclusive_scan(start ? 1u : 0u, wave_tot);
+            if (start) {
+                const int64_t e = rank + ex;
+                if (e < capacity) {
+                    // walk the run with a sliding window sum
+                    int64_t t = s0 + i, te = t, tp = t;
+                    uint32_t cur = b, best = b;
+                    while (t + 1 < nbx) {
+                        const uint32_t nb = cur + static_cast<uint32_t>(row[t + w]) -
+                                            static_cast<uint32_t>(row[t]);
+                        if (nb < thr) break;
+                        ++t;
+                        cur = nb;
+                        te = t;
+                        if (nb > best) { best = nb; tp = t; }
+                    }
+                    const int64_t lval = static_cast<int64_t>(nbx) * best - static_cast<int64_t>(ws.s1[sidx]);
+                    dedisp_event ev;
+                    ev.width_idx = wi;
+                    ev.dm_idx = d;
+                    ev.t_start = s0 + i;
+                    ev.t_end = te;
+                    ev.t_peak = tp;
+                    ev.b_peak = static_cast<int32_t>(best);
+                    ev.snr = static_cast<float>(static_cast<double>(lval) / ws.sqrt_d[sidx]);
+                    events[e] = ev;
+                }
+            }
+            // total starts in this slab (last thread's exclusive + own)
+            __shared__ uint32_t slab_total;
+            if (threadIdx.x == kThreads - 1) slab_total = ex + (start ? 1u : 0u);
+            __syncthreads();
+            rank += slab_total;
+            __syncthreads();
+        }
+    }
+}
+
+}  // namespace
+
+namespace dd {
+
+int segment_length(int w_max) {
+    // LDS holds L + w_max + 1 running sums.
+    int L = 8192;
+    while (L > 256 && static_cast<int64_t>(L + w_max + 1) * 4 > 60 * 1024) L >>= 1;
+    return L;
+}
+
+size_t peaks_lds_bytes(int L, int w_max) { return static_cast<size_t>(L + w_max + 1) * 4; }
+
+hipError_t set_lds_limit(const void* fn, size_t bytes) {
+    if (bytes <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+}
+
+hipError_t launch_boxcar(const void* in, int in_u16, int ndm, int64_t nout, const Widths& W,
+                         int dm_first, int dm_count, int32_t* out, hipStream_t s) {
+    (void)ndm;
+    const int w_max = W.w[W.n - 1];
+    const int64_t nbx = nout - w_max + 1;
+    const int L = segment_length(w_max);
+    const size_t lds = peaks_lds_bytes(L, w_max);
+    const dim3 grid(static_cast<unsigned>((nbx + L - 1) / L), static_cast<unsigned>(dm_count));
+    if (in_u16) {
+        set_lds_limit(reinterpret_cast<const void*>(boxcar_kernel<uint16_t>), lds);
+        hipLaunchKernelGGL(boxcar_kernel<uint16_t>, grid, dim3(kThreads), lds, s,
+                           static_cast<const uint16_t*>(in), nout, nbx, W, dm_first, L, out, dm_count);
+    } else {
+        set_lds_limit(reinterpret_cast<const void*>(boxcar_kernel<int32_t>), lds);
+        hipLaunchKernelGGL(boxcar_kernel<int32_t>, grid, dim3(kThreads), lds, s,
+                           static_cast<const int32_t*>(in), nout, nbx, W, dm_first, L, out, dm_count);
+    }
+    return hipGetLastError();
+}
+
+PeaksLayout peaks_layout(int ndm, int64_t nout, const Widths& W) {
+    PeaksLayout lay{};
+    const int w_max = W.w[W.n - 1];
+    lay.nbx = nout - w_max + 1;
+    lay.L = segment_length(w_max);
+    lay.nseg = static_cast<int>((lay.nbx + lay.L - 1) / lay.L);
+    lay.nseries = static_cast<int64_t>(W.n) * ndm;
+    lay.ncounts = lay.nseries * lay.nseg;
+    lay.nchunks = static_cast<int>((lay.ncounts + kScanChunk - 1) / kScanChunk);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    };
+    lay.o_part_s1 = take(lay.ncounts * 8);
+    lay.o_part_s2lo = take(lay.ncounts * 8);
+    lay.o_part_s2hi = take(lay.ncounts * 8);
+    lay.o_s1 = take(lay.nseries * 8);
+    lay.o_s2lo = take(lay.nseries * 8);
+    lay.o_s2hi = take(lay.nseries * 8);
+    lay.o_thr = take(lay.nseries * 8);
+    lay.o_thr32 = take(lay.nseries * 4);
+    lay.o_sqrt_d = take(lay.nseries * 8);
+    lay.o_counts = take(lay.ncounts * 4);
+    lay.o_offs = take(lay.ncounts * 8);
+    lay.o_chunk = take(static_cast<size_t>(lay.nchunks) * 8);
+    lay.o_total = take(8);
+    lay.bytes = off;
+    return lay;
+}
+
+PeaksWs peaks_ws(void* base, const PeaksLayout& lay) {
+    char* b = static_cast<char*>(base);
+    PeaksWs ws;
+    ws.part_s1 = reinterpret_cast<uint64_t*>(b + lay.o_part_s1);
+    ws.part_s2lo = reinterpret_cast<uint64_t*>(b + lay.o_part_s2lo);
+    ws.part_s2hi = reinterpret_cast<uint64_t*>(b + lay.o_part_s2hi);
+    ws.s1 = reinterpret_cast<uint64_t*>(b + lay.o_s1);
+    ws.s2lo = reinterpret_cast<uint64_t*>(b + lay.o_s2lo);
+    ws.s2hi = reinterpret_cast<uint64_t*>(b + lay.o_s2hi);
+    ws.thr = reinterpret_cast<int64_t*>(b + lay.o_thr);
+    ws.thr32 = reinterpret_cast<uint32_t*>(b + lay.o_thr32);
+    ws.sqrt_d = reinterpret_cast<double*>(b + lay.o_sqrt_d);
+    ws.counts = reinterpret_cast<uint32_t*>(b + lay.o_counts);
+    ws.offs = reinterpret_cast<int64_t*>(b + lay.o_offs);
+    ws.chunk_tot = reinterpret_cast<int64_t*>(b + lay.o_chunk);
+    ws.total = reinterpret_cast<int64_t*>(b + lay.o_total);
+    return ws;
+}
+
+hipError_t launch_peaks_count(const void* in, int in_u16, int ndm, int64_t nout, const Widths& W,
+                              const PeaksLayout& lay, const PeaksWs& ws, uint32_t kmant, int kexp2,
+                              hipStream_t s) {
+    const int w_max = W.w[W.n - 1];
+    const size_t lds = peaks_lds_bytes(lay.L, w_max);
+    const dim3 grid(static_cast<unsigned>(lay.nseg), static_cast<unsigned>(ndm));
+    if (in_u16) {
+        set_lds_limit(reinterpret_cast<const void*>(boxcar_stats_kernel<uint16_t>), lds);
+        hipLaunchKernelGGL(boxcar_stats_kernel<uint16_t>, grid, dim3(kThreads), lds, s,
+                           static_cast<const uint16_t*>(in), nout, lay.nbx, W, lay.L, lay.nseg, ws);
+    } else {
+        set_lds_limit(reinterpret_cast<const void*>(boxcar_stats_kernel<int32_t>), lds);
+        hipLaunchKernelGGL(boxcar_stats_kernel<int32_t>, grid, dim3(kThreads), lds, s,
+                           static_cast<const int32_t*>(in), nout, lay.nbx, W, lay.L, lay.nseg, ws);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nser = static_cast<int>(lay.nseries);
+    hipLaunchKernelGGL(series_threshold_kernel, dim3((nser + kThreads - 1) / kThreads), dim3(kThreads),
+                       0, s, nser, lay.nseg, lay.nbx, kmant, kexp2, ws);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (in_u16) {
+        set_lds_limit(reinterpret_cast<const void*>(peaks_count_kernel<uint16_t>), lds);
+        hipLaunchKernelGGL(peaks_count_kernel<uint16_t>, grid, dim3(kThreads), lds, s,
+                           static_cast<const uint16_t*>(in), nout, lay.nbx, W, lay.L, lay.nseg, ws);
+    } else {
+        set_lds_limit(reinterpret_cast<const void*>(peaks_count_kernel<int32_t>), lds);
+        hipLaunchKernelGGL(peaks_count_kernel<int32_t>, grid, dim3(kThreads), lds, s,
+                           static_cast<const int32_t*>(in), nout, lay.nbx, W, lay.L, lay.nseg, ws);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(scan_chunks_kernel, dim3(lay.nchunks), dim3(kThreads), 0, s, ws.counts,
+                       lay.ncounts, ws.offs, ws.chunk_tot);
+    hipLaunchKernelGGL(scan_totals_kernel, dim3(1), dim3(64), 0, s, ws.chunk_tot, lay.nchunks, ws.total);
+    hipLaunchKernelGGL(scan_add_kernel, dim3(static_cast<unsigned>((lay.ncounts + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, ws.offs, lay.ncounts, ws.chunk_tot);
+    return hipGetLastError();
+}
+
+hipError_t launch_peaks_write(const void* in, int in_u16, int ndm, int64_t nout, const Widths& W,
+                              const PeaksLayout& lay, const PeaksWs& ws, dedisp_event* events,
+                              int64_t capacity, hipStream_t s) {
+    const int w_max = W.w[W.n - 1];
+    const size_t lds = peaks_lds_bytes(lay.L, w_max);
+    const dim3 grid(static_cast<unsigned>(lay.nseg), static_cast<unsigned>(ndm));
+    if (in_u16) {
+        set_lds_limit(reinterpret_cast<const void*>(peaks_write_kernel<uint16_t>), lds);
+        hipLaunchKernelGGL(peaks_write_kernel<uint16_t>, grid, dim3(kThreads), lds, s,
+                           static_cast<const uint16_t*>(in), nout, lay.nbx, W, lay.L, lay.nseg, ws,
+                           events, capacity);
+    } else {
+        set_lds_limit(reinterpret_cast<const void*>(peaks_write_kernel<int32_t>), lds);
+        hipLaunchKernelGGL(peaks_write_kernel<int32_t>, grid, dim3(kThreads), lds, s,
+                           static_cast<const int32_t*>(in), nout, lay.nbx, W, lay.L, lay.nseg, ws,
+                           events, capacity);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dd

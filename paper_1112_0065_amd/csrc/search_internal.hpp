@@ -1,0 +1,64 @@
+// Internal declarations of the boxcar / sigma-cut / peak-finding stage.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/dedisp.h"
+
+namespace dd {
+
+constexpr int kMaxWidths = 32;
+
+// Boxcar widths, passed by value to kernels.
+struct Widths {
+    int32_t w[kMaxWidths];
+    int32_t n;
+};
+
+// Device workspace of find_peaks (all arrays live in one caller buffer).
+struct PeaksWs {
+    uint64_t* part_s1;     // [nw][ndm][nseg]
+    uint64_t* part_s2lo;   // [nw][ndm][nseg]
+    uint64_t* part_s2hi;   // [nw][ndm][nseg]
+    uint64_t* s1;          // [nw][ndm]
+    uint64_t* s2lo;        // [nw][ndm]
+    uint64_t* s2hi;        // [nw][ndm]
+    int64_t* thr;          // [nw][ndm], -1: no events (D == 0)
+    uint32_t* thr32;       // [nw][ndm], 0xFFFFFFFF: nothing can pass
+    double* sqrt_d;        // [nw][ndm]
+    uint32_t* counts;      // [nw][ndm][nseg] run starts
+    int64_t* offs;         // [nw][ndm][nseg] exclusive scan of counts
+    int64_t* chunk_tot;    // scan scratch
+    int64_t* total;        // total number of events
+};
+
+struct PeaksLayout {
+    int64_t nbx;
+    int L;
+    int nseg;
+    int64_t nseries;
+    int64_t ncounts;
+    int nchunks;
+    size_t o_part_s1, o_part_s2lo, o_part_s2hi, o_s1, o_s2lo, o_s2hi, o_thr, o_thr32, o_sqrt_d,
+        o_counts, o_offs, o_chunk, o_total;
+    size_t bytes;
+};
+
+int segment_length(int w_max);
+PeaksLayout peaks_layout(int ndm, int64_t nout, const Widths& W);
+PeaksWs peaks_ws(void* base, const PeaksLayout& lay);
+
+hipError_t launch_boxcar(const void* in, int in_u16, int ndm, int64_t nout, const Widths& W,
+                         int dm_first, int dm_count, int32_t* out, hipStream_t s);
+// Stats, thresholds, run-start counts and their scan (total in ws.total).
+hipError_t launch_peaks_count(const void* in, int in_u16, int ndm, int64_t nout, const Widths& W,
+                              const PeaksLayout& lay, const PeaksWs& ws, uint32_t kmant, int kexp2,
+                              hipStream_t s);
+hipError_t launch_peaks_write(const void* in, int in_u16, int ndm, int64_t nout, const Widths& W,
+                              const PeaksLayout& lay, const PeaksWs& ws, dedisp_event* events,
+                              int64_t capacity, hipStream_t s);
+
+}  // namespace dd

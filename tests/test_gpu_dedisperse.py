@@ -1,0 +1,192 @@
+"""GPU parity of the plan, the 2-bit ingest and the dedispersion kernel
+(section 2.2) against the oracle, through the C ABI.  Bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import log, small_case, survey_case, to_dev, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(fb_or_args):
+    from paper_1112_0065_amd import _lib as L
+    return L.dedisp_plan_create(*fb_or_args)
+
+
+def test_delay_tables_equal_oracle():
+    from paper_1112_0065_amd import _lib as L
+    for nchans, ft, df, dms in [
+        (256, 1581.8, -1.5625, synth.dm_list_linear(100, 200.0)),
+        (1024, 1581.8, -400.0 / 1024, synth.dm_list_expm1(1200, 1000.0)),
+        (64, 1400.0, -3.0, [0.0, 0.0, 10.0, 10.0, 55.5]),
+    ]:
+        p = L.dedisp_plan_create(nchans, ft, df, 64e-6, dms)
+        ref = oracle.delay_table(nchans, ft, df, 64e-6, dms)
+        got = L.dedisp_plan_copy_delays(p)
+        assert (got == ref).all()
+        assert p.max_delay == oracle.max_delay(ref)
+    log("delay tables ok")
+
+
+def _run(p, packed, nsamps, dtype, tile=None):
+    from paper_1112_0065_amd import _lib as L
+    torch = torch_dev()
+    inp = to_dev(packed)
+    out = torch.full((p.ndm, nsamps - p.max_delay), 0x5A5A, dtype=dtype, device="cuda")
+    ws = torch.empty(L.dedisp_workspace_bytes(p, nsamps), dtype=torch.uint8, device="cuda")
+    if tile is None:
+        L.dedisp_execute(p, inp, nsamps, out, ws)
+    else:
+        L.dedisp_execute_tile(p, inp, nsamps, out, ws, tile)
+    torch.cuda.synchronize()
+    return as_i64(out)
+
+
+def as_i64(out):
+    """Host int64 copy; 16-bit series are stored in int16 tensors and read as uint16."""
+    torch = torch_dev()
+    a = out.cpu().numpy()
+    if out.dtype == torch.int16:
+        a = a.view(np.uint16)
+    return a.astype(np.int64)
+
+
+def test_small_config_every_tile_both_dtypes():
+    from paper_1112_0065_amd import _lib as L
+    torch = torch_dev()
+    fb, dly, x, ref = small_case()
+    p = L.dedisp_plan_create(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list)
+    for tile in L.dedisp_tile_candidates():
+        for dtype in (torch.int16, torch.int32):
+            log("small config tile", tile, dtype)
+            got = _run(p, fb.packed, fb.nsamps, dtype, tile)
+            assert got.shape == ref.shape
+            bad = np.argwhere(got != ref)
+            assert bad.size == 0, (tile, dtype, bad[:5])
+
+
+def test_default_tile_and_determinism():
+    from paper_1112_0065_amd import _lib as L
+    torch = torch_dev()
+    fb, dly, x, ref = small_case()
+    p = L.dedisp_plan_create(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list)
+    a = _run(p, fb.packed, fb.nsamps, torch.int16)
+    b = _run(p, fb.packed, fb.nsamps, torch.int16)
+    assert (a == ref).all() and (a == b).all()
+
+
+@pytest.mark.parametrize("nchans,nsamps,dms,seed", [
+    (4, 100, [0.0], 1),                         # DM 0 only: plain channel sum
+    (8, 300, [0.0, 40.0, 80.0], 2),
+    (12, 2500, list(np.linspace(0, 300, 7)), 3),
+    (64, 6000, list(np.linspace(0, 120, 37)), 4),  # ragged DM blocks
+    (1364, 3000, [0.0, 1.0, 2.0, 5.0, 9.0], 5),    # largest 12-level counter
+    (1368, 3000, [0.0, 1.0, 2.0, 5.0, 9.0], 6),    # 16-level counter
+])
+def test_tiny_and_edge_shapes(nchans, nsamps, dms, seed):
+    torch = torch_dev()
+    from paper_1112_0065_amd import _lib as L
+    df = -400.0 / max(nchans, 64)
+    fb = synth.make_tiny(seed, nchans, nsamps, dms, df=df)
+    p = L.dedisp_plan_create(nchans, fb.f_top, df, fb.tsamp, dms)
+    dly = oracle.delay_table(nchans, fb.f_top, df, fb.tsamp, dms)
+    ref = oracle.dedisperse(oracle.unpack_2bit(fb.packed, nsamps, nchans), dly)
+    for dtype in (torch.int16, torch.int32):
+        for tile in [None, (4, 1, 16), (32, 1, 64), (16, 2, 32)]:
+            log("edge", nchans, nsamps, len(dms), dtype, tile)
+            got = _run(p, fb.packed, nsamps, dtype, tile)
+            assert (got == ref).all(), (nchans, dtype, tile)
+
+
+@pytest.mark.parametrize("extra", [1, 2, 31, 32, 33, 2047, 2048, 2049, 4095, 4097])
+def test_ragged_output_lengths(extra):
+    """nout just around multiples of the 32-sample group and the time tile."""
+    torch = torch_dev()
+    from paper_1112_0065_amd import _lib as L
+    nchans, dms = 32, [0.0, 25.0, 50.0]
+    df = -10.0
+    dly = oracle.delay_table(nchans, synth.F_TOP, df, synth.TSAMP, dms)
+    nsamps = int(dly.max()) + extra
+    fb = synth.make_tiny(extra, nchans, nsamps, dms, df=df)
+    p = L.dedisp_plan_create(nchans, fb.f_top, df, fb.tsamp, dms)
+    ref = oracle.dedisperse(oracle.unpack_2bit(fb.packed, nsamps, nchans), dly)
+    for dtype in (torch.int16, torch.int32):
+        got = _run(p, fb.packed, nsamps, dtype, (4, 2, 16))
+        assert got.shape == (3, extra) and (got == ref).all()
+
+
+def test_all_threes_maximum_sums():
+    """Every sample at level 3: each output equals 3*nchans (the range limit
+    of the 12- and 16-level counters and of uint16 at 21844 channels)."""
+    torch = torch_dev()
+    from paper_1112_0065_amd import _lib as L
+    for nchans, nsamps in [(1364, 700), (21844, 300)]:
+        dms = [0.0, 0.5]
+        df = -0.01
+        lv = np.full((nsamps, nchans), 3, np.uint8)
+        fb = synth.make_tiny(0, nchans, nsamps, dms, df=df, levels=lv)
+        p = L.dedisp_plan_create(nchans, fb.f_top, df, fb.tsamp, dms)
+        for dtype in (torch.int16, torch.int32):
+            got = _run(p, fb.packed, nsamps, dtype, (4, 1, 16))
+            assert (got == 3 * nchans).all()
+
+
+def test_too_few_samples_and_bad_args():
+    torch = torch_dev()
+    from paper_1112_0065_amd import _lib as L
+    p = L.dedisp_plan_create(16, 1500.0, -5.0, 64e-6, [0.0, 100.0])
+    buf = torch.zeros(16 * 4096 // 4, dtype=torch.uint8, device="cuda")
+    out = torch.zeros((2, 10), dtype=torch.int32, device="cuda")
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    with pytest.raises(L.DedispError) as e:
+        L.dedisp_execute(p, buf, p.max_delay, out, ws)
+    assert e.value.status == L.ERR_TOO_FEW_SAMPLES
+    with pytest.raises(L.DedispError) as e:
+        L.dedisp_execute_tile(p, buf, 4096, out, ws, (5, 1, 16))
+    assert e.value.status == L.ERR_INVALID_ARG
+    for bad in [(6, 1500.0, -5.0, 64e-6, [0.0]), (16, 1500.0, 5.0, 64e-6, [0.0]),
+                (16, 1500.0, -5.0, 0.0, [0.0]), (16, 1500.0, -5.0, 64e-6, [3.0, 1.0]),
+                (16, 1500.0, -5.0, 64e-6, [-1.0]), (16, 1500.0, -100.0, 64e-6, [0.0])]:
+        with pytest.raises(L.DedispError) as e:
+            L.dedisp_plan_create(*bad)
+        assert e.value.status == L.ERR_INVALID_ARG
+
+
+def test_survey_config_full_size_sampled_rows():
+    """Survey-shaped beam at full size (2^19 samples, 1024 channels, 1200
+    trials), default tile, both output types: sampled rows against the oracle
+    (first, last, each pulse's nearest trial, random)."""
+    torch = torch_dev()
+    from paper_1112_0065_amd import _lib as L
+    fb = survey_case()
+    p = L.dedisp_plan_create(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list)
+    dly = oracle.delay_table(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list)
+    assert p.max_delay == 20476
+    rng = np.random.default_rng(7)
+    rows = {0, len(fb.dm_list) - 1}
+    rows |= {int(np.argmin(np.abs(fb.dm_list - pu.dm))) for pu in fb.pulses[:6]}
+    rows |= set(rng.integers(0, len(fb.dm_list), 4).tolist())
+    rows = sorted(rows)
+    x = oracle.unpack_2bit(fb.packed, fb.nsamps, fb.nchans)
+    ref = oracle.dedisperse(x, dly[rows], nout=fb.nsamps - 20476)
+    inp = to_dev(fb.packed)
+    ws = torch.empty(L.dedisp_workspace_bytes(p, fb.nsamps), dtype=torch.uint8, device="cuda")
+    for dtype in (torch.int16, torch.int32):
+        out = torch.empty((1200, fb.nsamps - 20476), dtype=dtype, device="cuda")
+        log("survey full size", dtype)
+        L.dedisp_execute(p, inp, fb.nsamps, out, ws)
+        torch.cuda.synchronize()
+        got = as_i64(out[rows])
+        assert (got == ref).all(), dtype
+        # whole-output property: every trial's total equals the sum of the
+        # windows it reads (from per-channel running sums of the input)
+        tot = out.to(torch.int64).sum(dim=1).cpu().numpy()
+        cx = np.zeros((fb.nchans, fb.nsamps + 1), np.int64)
+        np.cumsum(x, axis=1, out=cx[:, 1:])
+        nout = fb.nsamps - 20476
+        ch = np.arange(fb.nchans)
+        want = np.array([int((cx[ch, dly[d] + nout] - cx[ch, dly[d]]).sum()) for d in range(1200)])
+        assert (tot == want).all(), dtype
+        del out

@@ -1,0 +1,174 @@
+"""GPU parity of the boxcar filter, the exact sigma-cut and peak finding
+(section 2.3) against the oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.peaks import series_events
+import synth
+from gpu_common import events_equal, log, small_case, small_search, survey_case, to_dev, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _series_dev(out_np, u16):
+    torch = torch_dev()
+    if u16:
+        return to_dev(out_np.astype(np.uint16).view(np.int16))
+    return to_dev(out_np.astype(np.int32))
+
+
+def test_boxcar_filter_small_config():
+    from paper_1112_0065_amd import _lib as L
+    torch = torch_dev()
+    fb, dly, x, out = small_case()
+    bw, _ = small_search()
+    for u16 in (False, True):
+        s = _series_dev(out, u16)
+        for first, count in [(0, 100), (37, 5), (99, 1)]:
+            dst = torch.empty((len(fb.widths), count, bw.shape[2]), dtype=torch.int32, device="cuda")
+            L.boxcar_filter(s, 100, out.shape[1], fb.widths, first, count, dst)
+            torch.cuda.synchronize()
+            assert (dst.cpu().numpy() == bw[:, first:first + count]).all(), (u16, first)
+
+
+def test_boxcar_uint32_wrap():
+    """Running sums far beyond 2^32 wrap; the windows stay exact."""
+    from paper_1112_0065_amd import _lib as L
+    torch = torch_dev()
+    s = np.full((2, 300000), 60000, dtype=np.int64)
+    s[1, ::7] = 0
+    ref = oracle.boxcar(s, [1, 16, 300])
+    dst = torch.empty((3, 2, ref.shape[2]), dtype=torch.int32, device="cuda")
+    L.boxcar_filter(_series_dev(s, False), 2, s.shape[1], [1, 16, 300], 0, 2, dst)
+    torch.cuda.synchronize()
+    assert (dst.cpu().numpy() == ref).all()
+
+
+def _find(series_np, widths, k, u16, capacity=1 << 16):
+    from paper_1112_0065_amd import _lib as L
+    torch = torch_dev()
+    ndm, nout = series_np.shape
+    s = _series_dev(series_np, u16)
+    ws = torch.empty(max(256, L.find_peaks_workspace_bytes(ndm, nout, widths)), dtype=torch.uint8,
+                     device="cuda")
+    ev = torch.empty(max(capacity, 1) * 40, dtype=torch.uint8, device="cuda")
+    n = L.find_peaks(s, ndm, nout, widths, k, ev, capacity, ws)
+    stats = L.find_peaks_read_stats(ws, ndm, nout, widths)
+    return L.events_from_buffer(ev, n), stats
+
+
+def _ref_stats(bw, k):
+    nw, ndm = bw.shape[:2]
+    s1 = np.empty((nw, ndm), np.int64)
+    s2 = np.empty((nw, ndm), object)
+    thr = np.empty((nw, ndm), np.int64)
+    for w in range(nw):
+        for d in range(ndm):
+            n, a, b = oracle.series_stats(bw[w, d])
+            s1[w, d], s2[w, d] = a, b
+            t = oracle.threshold_level(n, a, b, k)
+            thr[w, d] = -1 if t is None else t
+    return s1, s2, thr
+
+
+def test_find_peaks_small_config():
+    fb, dly, x, out = small_case()
+    bw, ref_ev = small_search()
+    s1, s2, thr = _ref_stats(bw, fb.snr_thresh)
+    assert len(ref_ev) > 0
+    for u16 in (False, True):
+        log("find_peaks small config u16", u16, "ref events", len(ref_ev))
+        ev, (g1, g2, gt) = _find(out, fb.widths, fb.snr_thresh, u16)
+        assert (g1 == s1).all() and (g2 == s2).all() and (gt == thr).all()
+        events_equal(ev, ref_ev)
+
+
+@pytest.mark.parametrize("k", [0.5, 1.0, 2.0, 2.75, 3.0, 4.5])
+def test_find_peaks_thresholds_and_ties(k):
+    """Random series with many events; k values with exact ties possible."""
+    rng = np.random.default_rng(int(k * 100))
+    series = rng.integers(0, 12, size=(9, 4000)).astype(np.int64)
+    series[3, 100:140] = 40        # a long run
+    series[5, :] = 7               # constant series: D = 0 for every width
+    series[6, 3990:] = 30          # run touching the end
+    series[7, :20] = 30            # run at the start
+    widths = [1, 2, 3, 8]
+    bw = oracle.boxcar(series, widths)
+    ref = oracle.find_events(bw, k)
+    s1, s2, thr = _ref_stats(bw, k)
+    for u16 in (False, True):
+        ev, (g1, g2, gt) = _find(series, widths, k, u16)
+        assert (g1 == s1).all() and (g2 == s2).all() and (gt == thr).all()
+        events_equal(ev, ref)
+
+
+def test_find_peaks_capacity_overflow():
+    from paper_1112_0065_amd import _lib as L
+    rng = np.random.default_rng(3)
+    series = rng.integers(0, 12, size=(4, 3000)).astype(np.int64)
+    widths = [1, 2]
+    ref = oracle.find_events(oracle.boxcar(series, widths), 1.0)
+    assert len(ref) > 20
+    with pytest.raises(L.DedispError) as e:
+        _find(series, widths, 1.0, False, capacity=10)
+    assert e.value.status == L.ERR_CAPACITY
+    ev, _ = _find(series, widths, 1.0, False, capacity=len(ref))
+    events_equal(ev, ref)
+
+
+def test_find_peaks_bad_args():
+    from paper_1112_0065_amd import _lib as L
+    series = np.zeros((2, 100), np.int64)
+    for widths, k, st in [([4, 2], 3.0, L.ERR_INVALID_ARG), ([1, 200], 3.0, L.ERR_TOO_FEW_SAMPLES),
+                          ([1], 0.0, L.ERR_INVALID_ARG), ([1], float("nan"), L.ERR_INVALID_ARG)]:
+        with pytest.raises(L.DedispError) as e:
+            _find(series, widths, k, False)
+        assert e.value.status == st
+
+
+def test_survey_search_sampled_series():
+    """Full-size survey beam: dedisperse + find_peaks on the GPU; the events
+    and statistics of sampled DM rows equal the oracle's for those rows."""
+    from paper_1112_0065_amd import _lib as L
+    torch = torch_dev()
+    fb = survey_case()
+    p = L.dedisp_plan_create(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list)
+    dly = oracle.delay_table(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list)
+    nout = fb.nsamps - p.max_delay
+    inp = to_dev(fb.packed)
+    ws = torch.empty(L.dedisp_workspace_bytes(p, fb.nsamps), dtype=torch.uint8, device="cuda")
+    out = torch.empty((1200, nout), dtype=torch.int16, device="cuda")
+    L.dedisp_execute(p, inp, fb.nsamps, out, ws)
+    pws = torch.empty(L.find_peaks_workspace_bytes(1200, nout, fb.widths), dtype=torch.uint8,
+                      device="cuda")
+    evb = torch.empty((1 << 20) * 40, dtype=torch.uint8, device="cuda")
+    n = L.find_peaks(out, 1200, nout, fb.widths, fb.snr_thresh, evb, 1 << 20, pws)
+    ev = L.events_from_buffer(evb, n)
+    g1, g2, gt = L.find_peaks_read_stats(pws, 1200, nout, fb.widths)
+    log("survey events", n)
+    keys = [(int(e["width_idx"]), int(e["dm_idx"]), int(e["t_start"])) for e in ev]
+    assert keys == sorted(keys)
+    rng = np.random.default_rng(11)
+    rows = sorted({0, 1199} | {int(np.argmin(np.abs(fb.dm_list - pu.dm))) for pu in fb.pulses[:4]}
+                  | set(rng.integers(0, 1200, 2).tolist()))
+    x = oracle.unpack_2bit(fb.packed, fb.nsamps, fb.nchans)
+    ref_rows = oracle.dedisperse(x, dly[rows], nout=nout)
+    for k, d in enumerate(rows):
+        bw = oracle.boxcar(ref_rows[k:k + 1], fb.widths)
+        for wi in range(len(fb.widths)):
+            nn, a, b = oracle.series_stats(bw[wi, 0])
+            assert g1[wi, d] == a and g2[wi, d] == b
+            t = oracle.threshold_level(nn, a, b, fb.snr_thresh)
+            assert gt[wi, d] == (-1 if t is None else t)
+            ref_ev = series_events(bw[wi, 0], fb.snr_thresh, wi, d)
+            got = [e for e in ev if int(e["width_idx"]) == wi and int(e["dm_idx"]) == d]
+            events_equal(got, ref_ev)
+    # every injected pulse with nominal S/N >= 12 is detected near its DM and time
+    for pu in fb.pulses:
+        if pu.snr < 12:
+            continue
+        d = int(np.argmin(np.abs(fb.dm_list - pu.dm)))
+        hit = [e for e in ev if abs(int(e["dm_idx"]) - d) <= 3 and
+               abs(int(e["t_peak"]) - pu.t0) <= pu.width + 64]
+        assert hit, (pu.dm, pu.t0, pu.width, pu.snr)
