@@ -135,6 +135,21 @@ dedisp_status dedisp_execute_tile(dedisp_plan plan, const uint8_t* in_2bit, int6
                                   void* out, dedisp_out_type out_type, void* workspace,
                                   const dedisp_tile* tile, dedisp_stream stream);
 
+/* The two kernels of dedisp_execute, callable separately (timing, and
+ * streaming callers that keep the bit-plane copy resident):
+ *   dedisp_repack: in_2bit (device, layout as dedisp_execute) -> workspace
+ *     (device, >= dedisp_workspace_bytes(plan, nsamps), 256-byte aligned),
+ *     the channel-major bit-plane copy: for channel c, word j holds samples
+ *     32j..32j+31 as two 32-bit planes (bit 0 and bit 1 of each level).
+ *   dedisp_execute_repacked: dedispersion from that copy; `tile` (host) may
+ *     be NULL for the default shape.
+ * Errors and asynchrony as dedisp_execute. */
+dedisp_status dedisp_repack(dedisp_plan plan, const uint8_t* in_2bit, int64_t nsamps,
+                            void* workspace, dedisp_stream stream);
+dedisp_status dedisp_execute_repacked(dedisp_plan plan, const void* workspace, int64_t nsamps,
+                                      void* out, dedisp_out_type out_type,
+                                      const dedisp_tile* tile, dedisp_stream stream);
+
 /* ------------------------------------------------------------------------
  * Boxcar matched filter (section 2.3), materialised for a DM sub-range:
  *   P[0] = 0, P[t+1] = P[t] + s[t];  B_w[t] = P[t+w] - P[t],

@@ -68,6 +68,8 @@ def lib() -> C.CDLL:
         "dedisp_tile_candidates": (i32, [P(_Tile), i32]),
         "dedisp_default_tile": (i32, [vp, P(_Tile)]),
         "dedisp_execute_tile": (i32, [vp, vp, i64, vp, i32, vp, P(_Tile), vp]),
+        "dedisp_repack": (i32, [vp, vp, i64, vp, vp]),
+        "dedisp_execute_repacked": (i32, [vp, vp, i64, vp, i32, P(_Tile), vp]),
         "boxcar_filter": (i32, [vp, i32, i32, i64, P(i32), i32, i32, i32, vp, vp]),
         "find_peaks_workspace_bytes": (sz, [i32, i64, P(i32), i32]),
         "find_peaks": (i32, [vp, i32, i32, i64, P(i32), i32, f32, vp, i64, P(i64), vp, vp]),
@@ -206,6 +208,17 @@ def dedisp_execute_tile(plan: Plan, in_2bit, nsamps: int, out, workspace, tile, 
     _check(lib().dedisp_execute_tile(plan.handle, _ptr(in_2bit), int(nsamps), _ptr(out),
                                      _out_type(out), _ptr(workspace), C.byref(t),
                                      _stream(stream)))
+
+
+def dedisp_repack(plan: Plan, in_2bit, nsamps: int, workspace, stream=None):
+    _check(lib().dedisp_repack(plan.handle, _ptr(in_2bit), int(nsamps), _ptr(workspace),
+                               _stream(stream)))
+
+
+def dedisp_execute_repacked(plan: Plan, workspace, nsamps: int, out, tile=None, stream=None):
+    t = None if tile is None else C.byref(_Tile(*[int(v) for v in tile]))
+    _check(lib().dedisp_execute_repacked(plan.handle, _ptr(workspace), int(nsamps), _ptr(out),
+                                         _out_type(out), t, _stream(stream)))
 
 
 def _out_type(t) -> int:

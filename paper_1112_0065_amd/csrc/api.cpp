@@ -55,11 +55,8 @@ dedisp_status split_threshold(float k, uint32_t* kmant, int* kexp2) {
 
 namespace dd {
 
-dedisp_status execute_with_tile(dedisp_plan p, const uint8_t* in, int64_t nsamps, void* out,
-                                dedisp_out_type out_type, void* workspace, const TileConfig& cfg,
-                                hipStream_t stream) {
-    if (!p || !in || !out || !workspace) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
-    if (!valid_type(out_type)) return fail(DEDISP_ERR_INVALID_ARG, "bad out_type");
+dedisp_status check_exec(dedisp_plan p, const void* workspace, int64_t nsamps) {
+    if (!p || !workspace) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
     if (nsamps <= p->max_delay)
         return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "nsamps=%lld <= max_delay=%lld",
                     static_cast<long long>(nsamps), static_cast<long long>(p->max_delay));
@@ -70,14 +67,40 @@ dedisp_status execute_with_tile(dedisp_plan p, const uint8_t* in, int64_t nsamps
     if (dev != p->device)
         return fail(DEDISP_ERR_INVALID_ARG, "current device %d differs from the plan's %d", dev,
                     p->device);
-    const int64_t nwords = repack_words(nsamps);
-    uint2* words = static_cast<uint2*>(workspace);
-    DD_HIP(launch_repack(in, nsamps, p->nchans, words, nwords, stream));
-    const int64_t nout = nsamps - p->max_delay;
-    const dedisp_status st =
-        launch_dedisperse(p, words, nwords, nout, out, out_type == DEDISP_OUT_U16, cfg, stream);
+    return DEDISP_OK;
+}
+
+dedisp_status repack(dedisp_plan p, const uint8_t* in, int64_t nsamps, void* workspace,
+                     hipStream_t stream) {
+    dedisp_status st = check_exec(p, workspace, nsamps);
+    if (st != DEDISP_OK) return st;
+    if (!in) return fail(DEDISP_ERR_INVALID_ARG, "NULL input");
+    DD_HIP(launch_repack(in, nsamps, p->nchans, static_cast<uint2*>(workspace),
+                         repack_words(nsamps), stream));
+    return DEDISP_OK;
+}
+
+dedisp_status execute_repacked(dedisp_plan p, const void* workspace, int64_t nsamps, void* out,
+                               dedisp_out_type out_type, const TileConfig& cfg,
+                               hipStream_t stream) {
+    dedisp_status st = check_exec(p, workspace, nsamps);
+    if (st != DEDISP_OK) return st;
+    if (!out) return fail(DEDISP_ERR_INVALID_ARG, "NULL output");
+    if (!valid_type(out_type)) return fail(DEDISP_ERR_INVALID_ARG, "bad out_type");
+    st = launch_dedisperse(p, static_cast<const uint2*>(workspace), repack_words(nsamps),
+                           nsamps - p->max_delay, out, out_type == DEDISP_OUT_U16, cfg, stream);
     if (st == DEDISP_OK) clear_error();
     return st;
+}
+
+dedisp_status execute_with_tile(dedisp_plan p, const uint8_t* in, int64_t nsamps, void* out,
+                                dedisp_out_type out_type, void* workspace, const TileConfig& cfg,
+                                hipStream_t stream) {
+    if (!p || !in || !out || !workspace) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
+    if (!valid_type(out_type)) return fail(DEDISP_ERR_INVALID_ARG, "bad out_type");
+    dedisp_status st = repack(p, in, nsamps, workspace, stream);
+    if (st != DEDISP_OK) return st;
+    return execute_repacked(p, workspace, nsamps, out, out_type, cfg, stream);
 }
 
 }  // namespace dd
@@ -115,19 +138,51 @@ extern "C" dedisp_status dedisp_default_tile(dedisp_plan p, dedisp_tile* out) {
     return DEDISP_OK;
 }
 
-extern "C" dedisp_status dedisp_execute_tile(dedisp_plan p, const uint8_t* in, int64_t nsamps,
-                                             void* out, dedisp_out_type out_type, void* workspace,
-                                             const dedisp_tile* tile, dedisp_stream stream) {
-    if (!p || !tile) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
+namespace {
+
+dedisp_status tile_from(const dedisp_tile* tile, dedisp_plan p, dd::TileConfig* cfg) {
+    if (!tile) {
+        *cfg = dd::default_tile_config(p);
+        return DEDISP_OK;
+    }
     bool ok = false;
     for (const auto& sh : kShapes)
         ok |= sh[0] == tile->dms_per_block && sh[1] == tile->groups;
     if (!ok || tile->stage_chans < 4 || tile->stage_chans > 128 || tile->stage_chans % 4)
         return fail(DEDISP_ERR_INVALID_ARG, "unsupported tile (%d, %d, %d)", tile->dms_per_block,
                     tile->groups, tile->stage_chans);
-    return dd::execute_with_tile(p, in, nsamps, out, out_type, workspace,
-                                 dd::TileConfig{tile->dms_per_block, tile->groups, tile->stage_chans},
-                                 stream);
+    *cfg = dd::TileConfig{tile->dms_per_block, tile->groups, tile->stage_chans};
+    return DEDISP_OK;
+}
+
+}  // namespace
+
+extern "C" dedisp_status dedisp_execute_tile(dedisp_plan p, const uint8_t* in, int64_t nsamps,
+                                             void* out, dedisp_out_type out_type, void* workspace,
+                                             const dedisp_tile* tile, dedisp_stream stream) {
+    if (!p || !tile) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
+    dd::TileConfig cfg;
+    dedisp_status st = tile_from(tile, p, &cfg);
+    if (st != DEDISP_OK) return st;
+    return dd::execute_with_tile(p, in, nsamps, out, out_type, workspace, cfg, stream);
+}
+
+extern "C" dedisp_status dedisp_repack(dedisp_plan p, const uint8_t* in, int64_t nsamps,
+                                       void* workspace, dedisp_stream stream) {
+    dedisp_status st = dd::repack(p, in, nsamps, workspace, stream);
+    if (st == DEDISP_OK) dd::clear_error();
+    return st;
+}
+
+extern "C" dedisp_status dedisp_execute_repacked(dedisp_plan p, const void* workspace,
+                                                 int64_t nsamps, void* out,
+                                                 dedisp_out_type out_type, const dedisp_tile* tile,
+                                                 dedisp_stream stream) {
+    if (!p) return fail(DEDISP_ERR_INVALID_ARG, "plan is NULL");
+    dd::TileConfig cfg;
+    dedisp_status st = tile_from(tile, p, &cfg);
+    if (st != DEDISP_OK) return st;
+    return dd::execute_repacked(p, workspace, nsamps, out, out_type, cfg, stream);
 }
 
 extern "C" dedisp_status boxcar_filter(const void* in, dedisp_out_type in_type, int32_t ndm,
