@@ -206,6 +206,58 @@ dedisp_status find_peaks_read_stats(const void* workspace, int32_t ndm, int64_t 
                                     uint64_t* s2_lo, uint64_t* s2_hi, int64_t* thr,
                                     dedisp_stream stream);
 
+/* ------------------------------------------------------------------------
+ * Multibeam batch (the receiver has 13 beams, section 1; the plan of the
+ * paper's discussion runs one beam per GPU -- here all beams share one GPU):
+ * every beam's dedispersion runs in ONE persistent kernel that pops
+ * (beam, time tile, DM block) work items, then each beam's boxcar /
+ * sigma-cut / peak chain runs; the whole sequence is captured once in a HIP
+ * graph and replayed, and re-captured when any beam's buffers, capacity or
+ * length change.  Results are bit-identical to the single-beam calls.
+ *
+ * dedisp_batch_create: plans (host array of nbeams plans, same device, same
+ *   counter width: all nchans <= 1365 or all > 1365; the plans must outlive
+ *   the batch), widths / snr_thresh as find_peaks, out_type of every beam's
+ *   series, tune_cache_path (NULL: the first plan's default tile shape; else
+ *   the cached autotuned shape for the first plan when present).
+ * dedisp_batch_execute: host arrays of nbeams entries: in_2bit (device
+ *   inputs), nsamps, out (device series [ndm_b][nsamps_b - max_delay_b]),
+ *   events (device, capacity_b records each), capacity, n_events (host
+ *   outputs: events found per beam).  Synchronises `stream`.  CAPACITY when a
+ *   beam found more events than its capacity (its first `capacity` written).
+ *   Not thread-safe per batch object.
+ * dedisp_batch_info: the tile shape, persistent grid size and number of
+ *   graph captures so far (any output may be NULL).
+ * ------------------------------------------------------------------------ */
+typedef struct dedisp_batch_s* dedisp_batch;
+dedisp_status dedisp_batch_create(const dedisp_plan* plans, int32_t nbeams,
+                                  const int32_t* widths, int32_t nwidths, float snr_thresh,
+                                  dedisp_out_type out_type, const char* tune_cache_path,
+                                  dedisp_batch* out);
+dedisp_status dedisp_batch_execute(dedisp_batch b, const uint8_t* const* in_2bit,
+                                   const int64_t* nsamps, void* const* out,
+                                   dedisp_event* const* events, const int64_t* capacity,
+                                   int64_t* n_events, dedisp_stream stream);
+dedisp_status dedisp_batch_info(dedisp_batch b, dedisp_tile* tile, int32_t* grid,
+                                int32_t* captures);
+dedisp_status dedisp_batch_destroy(dedisp_batch b);
+
+/* ------------------------------------------------------------------------
+ * Autotuner of the dedispersion tile shape for one plan and input length.
+ * Generates a deterministic pseudo-random input on the device, computes the
+ * output with a reference shape, and times only candidates whose output is
+ * bit-identical to it (others are counted in *n_rejected).  The fastest
+ * shape becomes the plan's default for dedisp_execute and, when cache_path
+ * is not NULL, is stored in that JSON file under the key
+ * "<gfx arch>:nchans=<n>:ndm=<next power of two>:<u16|i32>".  Plans created
+ * while the environment variable DEDISP_TUNE_CACHE names such a file start
+ * from its u16 entry.  best_out / n_rejected (host) may be NULL.
+ * Allocates about 2 output arrays + the input on the device; synchronous.
+ * ------------------------------------------------------------------------ */
+dedisp_status dedisp_autotune(dedisp_plan plan, int64_t nsamps, dedisp_out_type out_type,
+                              const char* cache_path, dedisp_tile* best_out,
+                              int32_t* n_rejected);
+
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* dedisp_last_error(void);
 

@@ -75,6 +75,11 @@ def lib() -> C.CDLL:
         "find_peaks": (i32, [vp, i32, i32, i64, P(i32), i32, f32, vp, i64, P(i64), vp, vp]),
         "find_peaks_read_stats": (i32, [vp, i32, i64, P(i32), i32, P(i64), P(C.c_uint64),
                                         P(C.c_uint64), P(i64), vp]),
+        "dedisp_batch_create": (i32, [P(vp), i32, P(i32), i32, f32, i32, C.c_char_p, P(vp)]),
+        "dedisp_batch_execute": (i32, [vp, P(vp), P(i64), P(vp), P(vp), P(i64), P(i64), vp]),
+        "dedisp_batch_info": (i32, [vp, P(_Tile), P(i32), P(i32)]),
+        "dedisp_batch_destroy": (i32, [vp]),
+        "dedisp_autotune": (i32, [vp, i64, i32, C.c_char_p, P(_Tile), P(i32)]),
         "dedisp_last_error": (C.c_char_p, []),
         "dedisp_version": (C.c_char_p, []),
     }
@@ -285,3 +290,64 @@ def events_from_buffer(buf, n: int) -> np.ndarray:
     if hasattr(raw, "cpu"):
         raw = raw.cpu().numpy()
     return np.frombuffer(np.asarray(raw, dtype=np.uint8).tobytes(), dtype=EVENT_DTYPE, count=n)
+
+
+# ---------------------------------------------------------------------------
+# Multibeam batch and autotuner
+# ---------------------------------------------------------------------------
+
+class Batch:
+    """Owns a dedisp_batch handle (and keeps its plans alive)."""
+
+    def __init__(self, handle: int, plans):
+        self.handle = handle
+        self.plans = list(plans)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.dedisp_batch_destroy(self.handle)
+            self.handle = None
+
+
+def dedisp_batch_create(plans, widths, snr_thresh: float, out_u16: bool = True,
+                        tune_cache_path: Optional[str] = None) -> Batch:
+    arr = (C.c_void_p * len(plans))(*[p.handle for p in plans])
+    h = C.c_void_p()
+    path = tune_cache_path.encode() if tune_cache_path else None
+    _check(lib().dedisp_batch_create(arr, len(plans), _i32arr(widths), len(widths),
+                                     float(snr_thresh), OUT_U16 if out_u16 else OUT_I32, path,
+                                     C.byref(h)))
+    return Batch(h.value, plans)
+
+
+def dedisp_batch_execute(batch: Batch, inputs, nsamps, outs, events, capacity, stream=None):
+    """inputs/outs/events: lists of device tensors (one per beam); returns the
+    list of event counts (raises DedispError(CAPACITY) on overflow)."""
+    n = len(batch.plans)
+    ins = (C.c_void_p * n)(*[_ptr(t) for t in inputs])
+    ns = (C.c_int64 * n)(*[int(v) for v in nsamps])
+    os_ = (C.c_void_p * n)(*[_ptr(t) for t in outs])
+    evs = (C.c_void_p * n)(*[_ptr(t) for t in events])
+    caps = (C.c_int64 * n)(*[int(v) for v in capacity])
+    cnt = (C.c_int64 * n)()
+    st = lib().dedisp_batch_execute(batch.handle, ins, ns, os_, evs, caps, cnt, _stream(stream))
+    if st == ERR_CAPACITY:
+        raise DedispError(st, dedisp_last_error() + f" (n_events={list(cnt)})")
+    _check(st)
+    return list(cnt)
+
+
+def dedisp_batch_info(batch: Batch):
+    t, g, c = _Tile(), C.c_int32(), C.c_int32()
+    _check(lib().dedisp_batch_info(batch.handle, C.byref(t), C.byref(g), C.byref(c)))
+    return (t.dms_per_block, t.groups, t.stage_chans), g.value, c.value
+
+
+def dedisp_autotune(plan: Plan, nsamps: int, out_u16: bool = True,
+                    cache_path: Optional[str] = None):
+    """Returns (best_tile, n_rejected)."""
+    t, rej = _Tile(), C.c_int32()
+    path = cache_path.encode() if cache_path else None
+    _check(lib().dedisp_autotune(plan.handle, int(nsamps), OUT_U16 if out_u16 else OUT_I32, path,
+                                 C.byref(t), C.byref(rej)))
+    return (t.dms_per_block, t.groups, t.stage_chans), rej.value

@@ -55,6 +55,14 @@ dedisp_status split_threshold(float k, uint32_t* kmant, int* kexp2) {
 
 namespace dd {
 
+dedisp_status split_threshold_public(float k, uint32_t* kmant, int* kexp2) {
+    return split_threshold(k, kmant, kexp2);
+}
+
+dedisp_status check_widths_public(const int32_t* widths, int32_t nwidths, int64_t nout, Widths* W) {
+    return check_widths(widths, nwidths, nout, W);
+}
+
 dedisp_status check_exec(dedisp_plan p, const void* workspace, int64_t nsamps) {
     if (!p || !workspace) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
     if (nsamps <= p->max_delay)

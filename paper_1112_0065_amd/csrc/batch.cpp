@@ -1,0 +1,270 @@
+// Multi-beam batch: all beams of a multibeam receiver (13 feed horns at
+// Parkes, paper section 1) dedispersed by one persistent launch, followed by
+// each beam's boxcar / sigma-cut / peak-finding chain, the whole sequence
+// captured once in a HIP graph and replayed per batch.
+//
+// The graph is re-captured whenever a beam's input, output, event buffer,
+// capacity or length changes.  Counters the persistent kernel pops work from
+// are cleared by a kernel inside the graph (no memset nodes).
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "dedisp_internal.hpp"
+#include "search_internal.hpp"
+
+using dd::fail;
+
+struct dedisp_batch_s {
+    std::vector<dedisp_plan> plans;
+    int nbeams = 0;
+    dd::Widths W{};
+    uint32_t kmant = 0;
+    int kexp2 = 0;
+    int out_u16 = 1;
+    dd::TileConfig cfg{};
+    int nl = 12;
+    size_t lds = 0;
+    int grid = 0;
+    int nq = 8;
+    dd::BeamArgs* d_beams = nullptr;
+    unsigned long long* d_counters = nullptr;
+    int64_t* h_totals = nullptr;   // pinned
+    std::vector<void*> words, pk_ws;
+    std::vector<size_t> words_bytes, pk_bytes;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // capture key
+    std::vector<const void*> k_in, k_out, k_ev;
+    std::vector<int64_t> k_nsamps, k_cap;
+    int64_t total_items = 0;
+    int captures = 0;
+};
+
+namespace dd {
+dedisp_status split_threshold_public(float k, uint32_t* kmant, int* kexp2);
+dedisp_status check_widths_public(const int32_t* widths, int32_t nwidths, int64_t nout, Widths* W);
+TileConfig tuned_or_default(const dedisp_plan_s* p, const char* cache_path, int out_u16);
+}  // namespace dd
+
+namespace {
+
+void release_graph(dedisp_batch_s* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+dedisp_status ensure(void*& ptr, size_t& have, size_t need) {
+    if (have >= need && ptr) return DEDISP_OK;
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    have = 0;
+    hipError_t e = hipMalloc(&ptr, need);
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? DEDISP_ERR_OUT_OF_MEMORY : DEDISP_ERR_HIP,
+                    "batch buffer of %zu bytes: %s", need, hipGetErrorString(e));
+    have = need;
+    return DEDISP_OK;
+}
+
+}  // namespace
+
+extern "C" dedisp_status dedisp_batch_create(const dedisp_plan* plans, int32_t nbeams,
+                                             const int32_t* widths, int32_t nwidths,
+                                             float snr_thresh, dedisp_out_type out_type,
+                                             const char* tune_cache_path, dedisp_batch* out) {
+    if (!out || !plans || nbeams < 1 || nbeams > 1024)
+        return fail(DEDISP_ERR_INVALID_ARG, "need 1..1024 plans and an output handle");
+    *out = nullptr;
+    if (out_type != DEDISP_OUT_I32 && out_type != DEDISP_OUT_U16)
+        return fail(DEDISP_ERR_INVALID_ARG, "bad out_type");
+    dd::Widths W;
+    dedisp_status st = dd::check_widths_public(widths, nwidths, INT64_C(1) << 30, &W);
+    if (st != DEDISP_OK) return st;
+    uint32_t km;
+    int ke;
+    st = dd::split_threshold_public(snr_thresh, &km, &ke);
+    if (st != DEDISP_OK) return st;
+    const int nl = dd::levels_for(plans[0] ? plans[0]->nchans : 4);
+    for (int i = 0; i < nbeams; ++i) {
+        if (!plans[i]) return fail(DEDISP_ERR_INVALID_ARG, "plan %d is NULL", i);
+        if (dd::levels_for(plans[i]->nchans) != nl)
+            return fail(DEDISP_ERR_UNSUPPORTED, "beams need the same counter width (nchans %d vs %d)",
+                        plans[i]->nchans, plans[0]->nchans);
+        if (plans[i]->device != plans[0]->device)
+            return fail(DEDISP_ERR_INVALID_ARG, "all plans must be on one device");
+    }
+    dedisp_batch_s* b = new (std::nothrow) dedisp_batch_s;
+    if (!b) return fail(DEDISP_ERR_OUT_OF_MEMORY, "host allocation failed");
+    b->plans.assign(plans, plans + nbeams);
+    b->nbeams = nbeams;
+    b->W = W;
+    b->kmant = km;
+    b->kexp2 = ke;
+    b->out_u16 = out_type == DEDISP_OUT_U16;
+    b->nl = nl;
+    b->cfg = dd::tuned_or_default(plans[0], tune_cache_path, b->out_u16);
+    for (int i = 0; i < nbeams; ++i) b->lds = std::max(b->lds, dd::tile_lds_bytes(plans[i], b->cfg));
+    if (b->lds > 160 * 1024) {
+        delete b;
+        return fail(DEDISP_ERR_UNSUPPORTED, "LDS tile of %zu bytes too large", b->lds);
+    }
+    int cus = 0;
+    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, plans[0]->device);
+    const int per_cu = dd::persistent_blocks_per_cu(nl, b->out_u16, b->cfg, b->lds);
+    if (e != hipSuccess || cus < 1 || per_cu < 1) {
+        delete b;
+        return fail(DEDISP_ERR_HIP, "occupancy query failed (%d CUs, %d blocks per CU)", cus, per_cu);
+    }
+    b->grid = ((cus * per_cu + b->nq - 1) / b->nq) * b->nq;
+    b->words.assign(nbeams, nullptr);
+    b->pk_ws.assign(nbeams, nullptr);
+    b->words_bytes.assign(nbeams, 0);
+    b->pk_bytes.assign(nbeams, 0);
+    e = hipMalloc(&b->d_beams, sizeof(dd::BeamArgs) * nbeams);
+    if (e == hipSuccess) e = hipMalloc(&b->d_counters, sizeof(unsigned long long) * b->nq);
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_totals, sizeof(int64_t) * nbeams, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        dedisp_batch_destroy(b);
+        return fail(DEDISP_ERR_HIP, "batch setup failed: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    dd::clear_error();
+    return DEDISP_OK;
+}
+
+extern "C" dedisp_status dedisp_batch_destroy(dedisp_batch b) {
+    if (!b) return fail(DEDISP_ERR_INVALID_ARG, "batch is NULL");
+    release_graph(b);
+    for (void* p : b->words)
+        if (p) (void)hipFree(p);
+    for (void* p : b->pk_ws)
+        if (p) (void)hipFree(p);
+    if (b->d_beams) (void)hipFree(b->d_beams);
+    if (b->d_counters) (void)hipFree(b->d_counters);
+    if (b->h_totals) (void)hipHostFree(b->h_totals);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+    return DEDISP_OK;
+}
+
+extern "C" dedisp_status dedisp_batch_info(dedisp_batch b, dedisp_tile* tile, int32_t* grid,
+                                           int32_t* captures) {
+    if (!b) return fail(DEDISP_ERR_INVALID_ARG, "batch is NULL");
+    if (tile) *tile = dedisp_tile{b->cfg.dms_per_block, b->cfg.groups, b->cfg.stage_chans};
+    if (grid) *grid = b->grid;
+    if (captures) *captures = b->captures;
+    return DEDISP_OK;
+}
+
+namespace {
+
+dedisp_status capture(dedisp_batch_s* b, const uint8_t* const* in, const int64_t* nsamps,
+                      void* const* out, dedisp_event* const* events, const int64_t* capacity) {
+    release_graph(b);
+    // Per-beam descriptors, item ranges laid end to end.
+    std::vector<dd::BeamArgs> args(b->nbeams);
+    int64_t total = 0;
+    for (int i = 0; i < b->nbeams; ++i) {
+        const dedisp_plan_s* p = b->plans[i];
+        const int64_t nout = nsamps[i] - p->max_delay;
+        args[i] = dd::beam_args(p, static_cast<const uint2*>(b->words[i]), dd::repack_words(nsamps[i]),
+                                nout, out[i], b->cfg);
+        args[i].item_begin = total;
+        total += args[i].n_items;
+    }
+    b->total_items = total;
+    DD_HIP(hipMemcpy(b->d_beams, args.data(), sizeof(dd::BeamArgs) * b->nbeams, hipMemcpyHostToDevice));
+
+    DD_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < b->nbeams && e == hipSuccess; ++i)
+        e = dd::launch_repack(in[i], nsamps[i], b->plans[i]->nchans, static_cast<uint2*>(b->words[i]),
+                              dd::repack_words(nsamps[i]), b->cap);
+    if (e == hipSuccess)
+        e = dd::launch_dedisperse_persistent(b->d_beams, b->nbeams, total, b->nl, b->out_u16, b->cfg,
+                                             b->lds, b->d_counters, b->nq, b->grid, b->cap);
+    for (int i = 0; i < b->nbeams && e == hipSuccess; ++i) {
+        const dedisp_plan_s* p = b->plans[i];
+        const int64_t nout = nsamps[i] - p->max_delay;
+        const dd::PeaksLayout lay = dd::peaks_layout(p->ndm, nout, b->W);
+        const dd::PeaksWs ws = dd::peaks_ws(b->pk_ws[i], lay);
+        e = dd::launch_peaks_count(out[i], b->out_u16, p->ndm, nout, b->W, lay, ws, b->kmant,
+                                   b->kexp2, b->cap);
+        if (e == hipSuccess && capacity[i] > 0)
+            e = dd::launch_peaks_write(out[i], b->out_u16, p->ndm, nout, b->W, lay, ws, events[i],
+                                       capacity[i], b->cap);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&b->h_totals[i], ws.total, sizeof(int64_t), hipMemcpyDeviceToHost,
+                               b->cap);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(DEDISP_ERR_HIP, "graph capture failed: %s",
+                    hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->graph = g;
+    DD_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+    b->captures++;
+    return DEDISP_OK;
+}
+
+}  // namespace
+
+extern "C" dedisp_status dedisp_batch_execute(dedisp_batch b, const uint8_t* const* in_2bit,
+                                              const int64_t* nsamps, void* const* out,
+                                              dedisp_event* const* events, const int64_t* capacity,
+                                              int64_t* n_events, dedisp_stream stream) {
+    if (!b || !in_2bit || !nsamps || !out || !events || !capacity || !n_events)
+        return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
+    const int w_max = b->W.w[b->W.n - 1];
+    for (int i = 0; i < b->nbeams; ++i) {
+        const dedisp_plan_s* p = b->plans[i];
+        if (!in_2bit[i] || !out[i] || capacity[i] < 0 || (capacity[i] > 0 && !events[i]))
+            return fail(DEDISP_ERR_INVALID_ARG, "beam %d: NULL buffer or negative capacity", i);
+        if (nsamps[i] - p->max_delay - w_max + 1 < 1)
+            return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "beam %d: %lld samples", i,
+                        static_cast<long long>(nsamps[i]));
+        if (nsamps[i] - p->max_delay - w_max + 1 >= (int64_t(1) << 31))
+            return fail(DEDISP_ERR_UNSUPPORTED, "beam %d too long", i);
+    }
+    bool changed = !b->exec || b->k_in.size() != static_cast<size_t>(b->nbeams);
+    for (int i = 0; i < b->nbeams && !changed; ++i)
+        changed = b->k_in[i] != in_2bit[i] || b->k_out[i] != out[i] || b->k_ev[i] != events[i] ||
+                  b->k_nsamps[i] != nsamps[i] || b->k_cap[i] != capacity[i];
+    if (changed) {
+        for (int i = 0; i < b->nbeams; ++i) {
+            const dedisp_plan_s* p = b->plans[i];
+            const int64_t nout = nsamps[i] - p->max_delay;
+            dedisp_status st = ensure(b->words[i], b->words_bytes[i],
+                                      static_cast<size_t>(p->nchans) * dd::repack_words(nsamps[i]) * sizeof(uint2));
+            if (st != DEDISP_OK) return st;
+            st = ensure(b->pk_ws[i], b->pk_bytes[i], dd::peaks_layout(p->ndm, nout, b->W).bytes);
+            if (st != DEDISP_OK) return st;
+        }
+        dedisp_status st = capture(b, in_2bit, nsamps, out, events, capacity);
+        if (st != DEDISP_OK) return st;
+        b->k_in.assign(in_2bit, in_2bit + b->nbeams);
+        b->k_out.assign(out, out + b->nbeams);
+        b->k_ev.assign(reinterpret_cast<const void* const*>(events),
+                       reinterpret_cast<const void* const*>(events) + b->nbeams);
+        b->k_nsamps.assign(nsamps, nsamps + b->nbeams);
+        b->k_cap.assign(capacity, capacity + b->nbeams);
+    }
+    DD_HIP(hipGraphLaunch(b->exec, stream));
+    DD_HIP(hipStreamSynchronize(stream));
+    dedisp_status st = DEDISP_OK;
+    for (int i = 0; i < b->nbeams; ++i) {
+        n_events[i] = b->h_totals[i];
+        if (n_events[i] > capacity[i]) st = DEDISP_ERR_CAPACITY;
+    }
+    if (st != DEDISP_OK) return fail(st, "a beam found more events than its capacity");
+    dd::clear_error();
+    return DEDISP_OK;
+}

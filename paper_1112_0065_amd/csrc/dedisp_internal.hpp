@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdarg>
 #include <cstdint>
 #include <string>
@@ -34,6 +35,21 @@ struct TileConfig {
     int stage_chans;     // channels per LDS stage (multiple of 4)
 };
 
+// Everything the dedispersion kernel needs about one beam.
+struct BeamArgs {
+    const uint2* words;      // channel-major bit-plane copy [nchans][nwords]
+    int64_t nwords;
+    int nchans;
+    int ndm;
+    int64_t nout;
+    const int32_t* delays;   // [ndm][nchans]
+    const int32_t* skew;     // per DM block, for the tile's block size
+    void* out;               // [ndm][nout]
+    int n_dm_blocks;
+    int64_t item_begin;      // first work item of this beam in a batch
+    int64_t n_items;         // time tiles x DM blocks
+};
+
 // Words (uint2 = one 32-sample lo/hi bit-plane pair) per channel in the
 // channel-major copy of the input.
 inline int64_t repack_words(int64_t nsamps) { return 2 * ((nsamps + 63) / 64) + 2; }
@@ -53,6 +69,8 @@ struct dedisp_plan_s {
     static constexpr int kNumDmBlock = 4;          // 4, 8, 16, 32 DMs
     int32_t* d_skew[kNumDmBlock] = {nullptr, nullptr, nullptr, nullptr};
     int32_t skew_max[kNumDmBlock] = {0, 0, 0, 0};
+    // Tile shape chosen by the autotuner (dms << 16 | groups << 8 | stage), 0 = default.
+    std::atomic<int> tuned{0};
 };
 
 namespace dd {
@@ -74,5 +92,16 @@ dedisp_status launch_dedisperse(const dedisp_plan_s* p, const uint2* words,
                                 int64_t nwords, int64_t nout, void* out, int out_u16,
                                 const TileConfig& cfg, hipStream_t s);
 TileConfig default_tile_config(const dedisp_plan_s* p);
+void apply_env_cache(dedisp_plan_s* p);
+BeamArgs beam_args(const dedisp_plan_s* p, const uint2* words, int64_t nwords, int64_t nout,
+                   void* out, const TileConfig& cfg);
+size_t tile_lds_bytes(const dedisp_plan_s* p, const TileConfig& cfg);
+// Persistent multi-beam launch (beams: device array, item ranges filled).
+hipError_t launch_dedisperse_persistent(const BeamArgs* d_beams, int nbeams, int64_t total,
+                                        int nl, int out_u16, const TileConfig& cfg, size_t lds,
+                                        unsigned long long* d_counters, int nq, int grid,
+                                        hipStream_t s);
+// Resident blocks per CU of the persistent kernel for this shape (0 on error).
+int persistent_blocks_per_cu(int nl, int out_u16, const TileConfig& cfg, size_t lds);
 
 }  // namespace dd

@@ -64,33 +64,17 @@ __device__ __forceinline__ void accumulate_chunk(uint32_t (&acc)[G][NL], const u
     }
 }
 
+// One work item: DM block `dblk` x time tile `tile` of one beam.
 template <int NL, int NDW, int G, bool OUT16>
-__global__ __launch_bounds__(kThreads) void dedisperse_kernel(
-    const uint2* __restrict__ words, int64_t nwords, int nchans, int ndm, int64_t nout,
-    const int32_t* __restrict__ delays, const int32_t* __restrict__ skew, int stage_chans,
-    int n_dm_blocks, int n_items, void* __restrict__ out) {
+__device__ __forceinline__ void process_item(const dd::BeamArgs& a, int tile, int dblk,
+                                             int stage_chans, uint2* lds, int lane, int wave) {
     constexpr int ND = NDW * kWaves;
     constexpr int T = 2048 * G;
-    extern __shared__ uint2 lds[];
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-
-    // XCD-aware order: hardware deals consecutive blocks round-robin to the 8
-    // XCDs; give each XCD a contiguous run of (time tile, DM block) items with
-    // the DM block fastest, so blocks resident on one XCD share input words in
-    // its L2.
-    const int per_xcd = gridDim.x / 8;
-    const int item = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    if (item >= n_items) return;
-    const int tile = item / n_dm_blocks;
-    const int dblk = item % n_dm_blocks;
     const int64_t T0 = static_cast<int64_t>(tile) * T;
     const int d_lo = dblk * ND;
-    const int stride = T / 32 + 1 + skew[dblk];
+    const int stride = T / 32 + 1 + a.skew[dblk];
     const int64_t w_base = T0 >> 5;
-    const int32_t* dlo_row = delays + static_cast<int64_t>(d_lo) * nchans;
+    const int32_t* dlo_row = a.delays + static_cast<int64_t>(d_lo) * a.nchans;
 
     uint32_t acc[NDW][G][NL];
 #pragma unroll
@@ -101,17 +85,17 @@ __global__ __launch_bounds__(kThreads) void dedisperse_kernel(
             for (int l = 0; l < NL; ++l) acc[i][g][l] = 0u;
 
 #pragma unroll 1
-    for (int c0 = 0; c0 < nchans; c0 += stage_chans) {
-        const int cs = min(stage_chans, nchans - c0);
+    for (int c0 = 0; c0 < a.nchans; c0 += stage_chans) {
+        const int cs = min(stage_chans, a.nchans - c0);
         // Stage fill: channel cl gets words [w_base + (delay[d_lo][c] >> 5), +stride).
         for (int cl = wave; cl < cs; cl += kWaves) {
             const int c = c0 + cl;
             const int64_t w0 = w_base + (dlo_row[c] >> 5);
-            const uint2* src = words + static_cast<int64_t>(c) * nwords;
+            const uint2* src = a.words + static_cast<int64_t>(c) * a.nwords;
             uint2* dst = lds + cl * stride;
             for (int i = lane; i < stride; i += 64) {
                 const int64_t w = w0 + i;
-                dst[i] = w < nwords ? src[w] : make_uint2(0u, 0u);
+                dst[i] = w < a.nwords ? src[w] : make_uint2(0u, 0u);
             }
         }
         __syncthreads();
@@ -119,8 +103,8 @@ __global__ __launch_bounds__(kThreads) void dedisperse_kernel(
 #pragma unroll
         for (int i = 0; i < NDW; ++i) {
             const int d = d_lo + wave + kWaves * i;
-            if (d < ndm) {
-                const int32_t* drow = delays + static_cast<int64_t>(d) * nchans;
+            if (d < a.ndm) {
+                const int32_t* drow = a.delays + static_cast<int64_t>(d) * a.nchans;
                 int cl = 0;
 #pragma unroll 1
                 for (; cl + 16 <= cs; cl += 16)
@@ -143,13 +127,13 @@ __global__ __launch_bounds__(kThreads) void dedisperse_kernel(
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int64_t t = T0 + 32 * (lane + 64 * g);
-            if (d >= ndm || t >= nout) continue;
+            if (d >= a.ndm || t >= a.nout) continue;
             uint32_t r[16];
             bs::planes_to_pairs<NL>(acc[i][g], r);
-            const int64_t row = static_cast<int64_t>(d) * nout;
-            const bool full = t + 32 <= nout;
+            const int64_t row = static_cast<int64_t>(d) * a.nout;
+            const bool full = t + 32 <= a.nout;
             if (OUT16) {
-                uint16_t* o = static_cast<uint16_t*>(out) + row + t;
+                uint16_t* o = static_cast<uint16_t*>(a.out) + row + t;
                 if (full && ((row + t) & 1) == 0) {
                     uint32_t* o32 = reinterpret_cast<uint32_t*>(o);
 #pragma unroll
@@ -159,13 +143,13 @@ __global__ __launch_bounds__(kThreads) void dedisperse_kernel(
                     for (int q = 0; q < 8; ++q)
                         o32[8 + q] = (r[2 * q] >> 16) | (r[2 * q + 1] & 0xFFFF0000u);
                 } else {
-                    const int n = static_cast<int>(min<int64_t>(32, nout - t));
+                    const int n = static_cast<int>(min<int64_t>(32, a.nout - t));
 #pragma unroll
                     for (int b = 0; b < 32; ++b)
                         if (b < n) o[b] = static_cast<uint16_t>(b < 16 ? r[b] : (r[b - 16] >> 16));
                 }
             } else {
-                int32_t* o = static_cast<int32_t*>(out) + row + t;
+                int32_t* o = static_cast<int32_t*>(a.out) + row + t;
                 if (full && ((row + t) & 3) == 0) {
                     int4* o4 = reinterpret_cast<int4*>(o);
 #pragma unroll
@@ -177,7 +161,7 @@ __global__ __launch_bounds__(kThreads) void dedisperse_kernel(
                         o4[4 + q] = make_int4(r[4 * q] >> 16, r[4 * q + 1] >> 16,
                                               r[4 * q + 2] >> 16, r[4 * q + 3] >> 16);
                 } else {
-                    const int n = static_cast<int>(min<int64_t>(32, nout - t));
+                    const int n = static_cast<int>(min<int64_t>(32, a.nout - t));
 #pragma unroll
                     for (int b = 0; b < 32; ++b)
                         if (b < n) o[b] = static_cast<int32_t>(b < 16 ? (r[b] & 0xFFFFu) : (r[b - 16] >> 16));
@@ -188,14 +172,60 @@ __global__ __launch_bounds__(kThreads) void dedisperse_kernel(
 }
 
 template <int NL, int NDW, int G, bool OUT16>
-hipError_t launch_cfg(const dedisp_plan_s* p, const uint2* words, int64_t nwords, int64_t nout,
-                      void* out, int stage_chans, hipStream_t s) {
-    constexpr int ND = NDW * kWaves;
-    constexpr int T = 2048 * G;
-    const int k = dd::dm_block_index(ND);
-    const int n_time_tiles = static_cast<int>((nout + T - 1) / T);
-    const int n_dm_blocks = (p->ndm + ND - 1) / ND;
-    const size_t lds = static_cast<size_t>(stage_chans) * (T / 32 + 1 + p->skew_max[k]) * sizeof(uint2);
+__global__ __launch_bounds__(kThreads) void dedisperse_kernel(dd::BeamArgs a, int stage_chans,
+                                                              int n_items) {
+    extern __shared__ uint2 lds[];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // XCD-aware order: hardware deals consecutive blocks round-robin to the 8
+    // XCDs; give each XCD a contiguous run of (time tile, DM block) items with
+    // the DM block fastest, so blocks resident on one XCD share input words in
+    // its L2.
+    const int per_xcd = gridDim.x / 8;
+    const int item = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (item >= n_items) return;
+    process_item<NL, NDW, G, OUT16>(a, item / a.n_dm_blocks, item % a.n_dm_blocks, stage_chans,
+                                    lds, lane, wave);
+}
+
+// Persistent form over the work items of several beams: blocks pop items
+// from `nq` queues (block b serves queue b % nq; queue q owns the contiguous
+// item range [q*total/nq, (q+1)*total/nq)), so that the blocks of one XCD work
+// through neighbouring (beam, time tile, DM block) items.  Every block leaves
+// once its queue is drained.
+template <int NL, int NDW, int G, bool OUT16>
+__global__ __launch_bounds__(kThreads) void dedisperse_persistent_kernel(
+    const dd::BeamArgs* __restrict__ beams, int nbeams, int64_t total, int stage_chans,
+    unsigned long long* __restrict__ counters, int nq) {
+    extern __shared__ uint2 lds[];
+    __shared__ long long item_sh;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int q = blockIdx.x % nq;
+    const int64_t q_lo = total * q / nq;
+    const int64_t q_hi = total * (q + 1) / nq;
+    for (;;) {
+        if (threadIdx.x == 0) item_sh = static_cast<long long>(q_lo + atomicAdd(&counters[q], 1ull));
+        __syncthreads();
+        const int64_t item = item_sh;
+        __syncthreads();
+        if (item >= q_hi) break;
+        int b = 0;
+        while (b + 1 < nbeams && item >= beams[b + 1].item_begin) ++b;
+        const dd::BeamArgs& a = beams[b];
+        const int64_t local = item - a.item_begin;
+        process_item<NL, NDW, G, OUT16>(a, static_cast<int>(local / a.n_dm_blocks),
+                                        static_cast<int>(local % a.n_dm_blocks), stage_chans, lds,
+                                        lane, wave);
+    }
+}
+
+__global__ void zero_counters_kernel(unsigned long long* c, int n) {
+    if (static_cast<int>(threadIdx.x) < n) c[threadIdx.x] = 0ull;
+}
+
+template <int NL, int NDW, int G, bool OUT16>
+hipError_t launch_cfg(const dd::BeamArgs& a, int stage_chans, size_t lds, hipStream_t s) {
     auto kern = dedisperse_kernel<NL, NDW, G, OUT16>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -203,23 +233,76 @@ hipError_t launch_cfg(const dedisp_plan_s* p, const uint2* words, int64_t nwords
                                            static_cast<int>(lds));
         if (e != hipSuccess) return e;
     }
-    const int64_t n_items = static_cast<int64_t>(n_time_tiles) * n_dm_blocks;
-    if (n_items > (int64_t(1) << 30)) return hipErrorInvalidValue;
-    const int64_t nblocks = 8 * ((n_items + 7) / 8);
-    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(nblocks)), dim3(kThreads), lds, s, words,
-                       nwords, p->nchans, p->ndm, nout, p->d_delays, p->d_skew[k], stage_chans,
-                       n_dm_blocks, static_cast<int>(n_items), out);
+    if (a.n_items > (int64_t(1) << 30)) return hipErrorInvalidValue;
+    const int64_t nblocks = 8 * ((a.n_items + 7) / 8);
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(nblocks)), dim3(kThreads), lds, s, a,
+                       stage_chans, static_cast<int>(a.n_items));
     return hipGetLastError();
+}
+
+template <int NL, int NDW, int G, bool OUT16>
+hipError_t launch_persistent_cfg(const dd::BeamArgs* beams, int nbeams, int64_t total,
+                                 int stage_chans, size_t lds, unsigned long long* counters, int nq,
+                                 int grid, hipStream_t s) {
+    auto kern = dedisperse_persistent_kernel<NL, NDW, G, OUT16>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, s, counters, nq);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, beams, nbeams, total, stage_chans,
+                       counters, nq);
+    return hipGetLastError();
+}
+
+template <int NL, int NDW, int G, bool OUT16>
+int occupancy_cfg(size_t lds) {
+    auto kern = dedisperse_persistent_kernel<NL, NDW, G, OUT16>;
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
+        return 0;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, kThreads, lds) != hipSuccess) return 0;
+    return n;
 }
 
 }  // namespace
 
 namespace dd {
 
-TileConfig default_tile_config(const dedisp_plan_s* p) {
-    (void)p;
-    return TileConfig{16, 2, 32};
+
+size_t tile_lds_bytes(const dedisp_plan_s* p, const TileConfig& cfg) {
+    const int k = dm_block_index(cfg.dms_per_block);
+    if (k < 0) return 0;
+    return static_cast<size_t>(cfg.stage_chans) * (2048 * cfg.groups / 32 + 1 + p->skew_max[k]) *
+           sizeof(uint2);
 }
+
+BeamArgs beam_args(const dedisp_plan_s* p, const uint2* words, int64_t nwords, int64_t nout,
+                   void* out, const TileConfig& cfg) {
+    const int k = dm_block_index(cfg.dms_per_block);
+    BeamArgs a{};
+    a.words = words;
+    a.nwords = nwords;
+    a.nchans = p->nchans;
+    a.ndm = p->ndm;
+    a.nout = nout;
+    a.delays = p->d_delays;
+    a.skew = k >= 0 ? p->d_skew[k] : nullptr;
+    a.out = out;
+    a.n_dm_blocks = (p->ndm + cfg.dms_per_block - 1) / cfg.dms_per_block;
+    const int64_t T = 2048 * cfg.groups;
+    a.item_begin = 0;
+    a.n_items = ((nout + T - 1) / T) * a.n_dm_blocks;
+    return a;
+}
+
+#define DD_SHAPES(X)                                                                   \
+    X(12, 1, 1) X(12, 2, 1) X(12, 4, 1) X(12, 8, 1) X(12, 1, 2) X(12, 2, 2) X(12, 4, 2)   \
+    X(16, 1, 1) X(16, 2, 1) X(16, 4, 1) X(16, 8, 1) X(16, 1, 2) X(16, 2, 2) X(16, 4, 2)
 
 dedisp_status launch_dedisperse(const dedisp_plan_s* p, const uint2* words, int64_t nwords,
                                 int64_t nout, void* out, int out_u16, const TileConfig& cfg,
@@ -227,28 +310,50 @@ dedisp_status launch_dedisperse(const dedisp_plan_s* p, const uint2* words, int6
     const int k = dm_block_index(cfg.dms_per_block);
     if (k < 0 || cfg.stage_chans < 4 || cfg.stage_chans % 4 || cfg.groups < 1 || cfg.groups > 2)
         return fail(DEDISP_ERR_INVALID_ARG, "unsupported tile configuration");
-    const int T = 2048 * cfg.groups;
-    const size_t lds = static_cast<size_t>(cfg.stage_chans) * (T / 32 + 1 + p->skew_max[k]) * sizeof(uint2);
+    const size_t lds = tile_lds_bytes(p, cfg);
     if (lds > 160 * 1024)
         return fail(DEDISP_ERR_UNSUPPORTED,
                     "DM block of %d trials spans %d words of skew: LDS tile of %zu bytes too large",
                     cfg.dms_per_block, p->skew_max[k], lds);
     const int nl = levels_for(p->nchans);
+    const BeamArgs a = beam_args(p, words, nwords, nout, out, cfg);
     hipError_t e = hipErrorInvalidValue;
-#define DD_DISPATCH(NL_, NDW_, G_)                                                               \
-    if (nl == NL_ && cfg.dms_per_block == NDW_ * kWaves && cfg.groups == G_) {                  \
-        e = out_u16 ? launch_cfg<NL_, NDW_, G_, true>(p, words, nwords, nout, out, cfg.stage_chans, s) \
-                    : launch_cfg<NL_, NDW_, G_, false>(p, words, nwords, nout, out, cfg.stage_chans, s); \
-    }
-    DD_DISPATCH(12, 1, 1) DD_DISPATCH(12, 2, 1) DD_DISPATCH(12, 4, 1) DD_DISPATCH(12, 8, 1)
-    DD_DISPATCH(12, 1, 2) DD_DISPATCH(12, 2, 2) DD_DISPATCH(12, 4, 2)
-    DD_DISPATCH(16, 1, 1) DD_DISPATCH(16, 2, 1) DD_DISPATCH(16, 4, 1) DD_DISPATCH(16, 8, 1)
-    DD_DISPATCH(16, 1, 2) DD_DISPATCH(16, 2, 2) DD_DISPATCH(16, 4, 2)
+#define DD_DISPATCH(NL_, NDW_, G_)                                                    \
+    if (nl == NL_ && cfg.dms_per_block == NDW_ * kWaves && cfg.groups == G_)          \
+        e = out_u16 ? launch_cfg<NL_, NDW_, G_, true>(a, cfg.stage_chans, lds, s)     \
+                    : launch_cfg<NL_, NDW_, G_, false>(a, cfg.stage_chans, lds, s);
+    DD_SHAPES(DD_DISPATCH)
 #undef DD_DISPATCH
     if (e != hipSuccess)
         return fail(e == hipErrorInvalidValue ? DEDISP_ERR_UNSUPPORTED : DEDISP_ERR_HIP,
                     "dedispersion launch failed: %s", hipGetErrorString(e));
     return DEDISP_OK;
+}
+
+hipError_t launch_dedisperse_persistent(const BeamArgs* d_beams, int nbeams, int64_t total,
+                                        int nl, int out_u16, const TileConfig& cfg, size_t lds,
+                                        unsigned long long* d_counters, int nq, int grid,
+                                        hipStream_t s) {
+    hipError_t e = hipErrorInvalidValue;
+#define DD_DISPATCH(NL_, NDW_, G_)                                                              \
+    if (nl == NL_ && cfg.dms_per_block == NDW_ * kWaves && cfg.groups == G_)                    \
+        e = out_u16 ? launch_persistent_cfg<NL_, NDW_, G_, true>(d_beams, nbeams, total,        \
+                          cfg.stage_chans, lds, d_counters, nq, grid, s)                        \
+                    : launch_persistent_cfg<NL_, NDW_, G_, false>(d_beams, nbeams, total,       \
+                          cfg.stage_chans, lds, d_counters, nq, grid, s);
+    DD_SHAPES(DD_DISPATCH)
+#undef DD_DISPATCH
+    return e;
+}
+
+int persistent_blocks_per_cu(int nl, int out_u16, const TileConfig& cfg, size_t lds) {
+    int n = 0;
+#define DD_DISPATCH(NL_, NDW_, G_)                                                   \
+    if (nl == NL_ && cfg.dms_per_block == NDW_ * kWaves && cfg.groups == G_)         \
+        n = out_u16 ? occupancy_cfg<NL_, NDW_, G_, true>(lds) : occupancy_cfg<NL_, NDW_, G_, false>(lds);
+    DD_SHAPES(DD_DISPATCH)
+#undef DD_DISPATCH
+    return n;
 }
 
 }  // namespace dd

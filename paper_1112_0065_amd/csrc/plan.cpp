@@ -136,6 +136,7 @@ extern "C" dedisp_status dedisp_plan_create(int32_t nchans, double f_top, double
         return fail(e == hipErrorOutOfMemory ? DEDISP_ERR_OUT_OF_MEMORY : DEDISP_ERR_HIP,
                     "device setup of the plan failed: %s", hipGetErrorString(e));
     }
+    dd::apply_env_cache(p);
     *plan_out = p;
     dd::clear_error();
     return DEDISP_OK;

@@ -1,0 +1,148 @@
+"""GPU tests of the multibeam batch (one persistent launch + graph replay)
+and of the tile autotuner: results identical to the single-beam path and to
+the oracle."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import events_equal, log, small_case, to_dev, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+WIDTHS = [1, 2, 4, 8, 16]
+
+
+def _beams(n, nchans=256, ndm=64):
+    """Uneven beams: lengths and DM ranges differ per beam (as in a
+    multibeam receiver whose beams are processed with their own plans)."""
+    out = []
+    for b in range(n):
+        nsamps = 24000 + 5000 * b
+        dm_max = 60.0 + 25.0 * ((5 * b) % 7)
+        fb = synth.make_beam(500 + b, nsamps, dm_max, 3, nchans=nchans, df=-400.0 / nchans,
+                             ndm=ndm, widths=WIDTHS, snr_thresh=5.0, name=f"b{b}")
+        out.append(fb)
+    return out
+
+
+def _single(plan, fb, inp, out_dtype, torch, L):
+    nout = fb.nsamps - plan.max_delay
+    out = torch.empty((plan.ndm, nout), dtype=out_dtype, device="cuda")
+    ws = torch.empty(L.dedisp_workspace_bytes(plan, fb.nsamps), dtype=torch.uint8, device="cuda")
+    L.dedisp_execute(plan, inp, fb.nsamps, out, ws)
+    pws = torch.empty(L.find_peaks_workspace_bytes(plan.ndm, nout, WIDTHS), dtype=torch.uint8,
+                      device="cuda")
+    evb = torch.empty(4096 * 40, dtype=torch.uint8, device="cuda")
+    n = L.find_peaks(out, plan.ndm, nout, WIDTHS, 5.0, evb, 4096, pws)
+    return out, L.events_from_buffer(evb, n)
+
+
+@pytest.mark.parametrize("u16", [True, False])
+def test_batch_equals_single_beam_and_oracle(u16):
+    from paper_1112_0065_amd import _lib as L
+    torch = torch_dev()
+    fbs = _beams(6)
+    plans = [L.dedisp_plan_create(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list) for fb in fbs]
+    dt = torch.int16 if u16 else torch.int32
+    ins = [to_dev(fb.packed) for fb in fbs]
+    outs = [torch.empty((p.ndm, fb.nsamps - p.max_delay), dtype=dt, device="cuda")
+            for p, fb in zip(plans, fbs)]
+    evs = [torch.empty(4096 * 40, dtype=torch.uint8, device="cuda") for _ in fbs]
+    batch = L.dedisp_batch_create(plans, WIDTHS, 5.0, out_u16=u16)
+    tile, grid, caps = L.dedisp_batch_info(batch)
+    log("batch tile", tile, "grid", grid)
+    counts = L.dedisp_batch_execute(batch, ins, [fb.nsamps for fb in fbs], outs, evs, [4096] * 6)
+    assert L.dedisp_batch_info(batch)[2] == 1
+    for b, (p, fb) in enumerate(zip(plans, fbs)):
+        s_out, s_ev = _single(p, fb, ins[b], dt, torch, L)
+        assert torch.equal(outs[b], s_out), b
+        b_ev = L.events_from_buffer(evs[b], counts[b])
+        assert b_ev.tobytes() == s_ev.tobytes(), b
+    # two beams against the oracle
+    for b in (0, 5):
+        fb = fbs[b]
+        dly = oracle.delay_table(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list)
+        ref = oracle.dedisperse(oracle.unpack_2bit(fb.packed, fb.nsamps, fb.nchans), dly)
+        got = outs[b].cpu().numpy()
+        got = (got.view(np.uint16) if u16 else got).astype(np.int64)
+        assert (got == ref).all()
+        events_equal(L.events_from_buffer(evs[b], counts[b]),
+                     oracle.find_events(oracle.boxcar(ref, WIDTHS), 5.0))
+
+
+def test_batch_replays_and_recapture():
+    """Graph replays with eager work in between give identical results; a
+    changed length re-captures and stays exact."""
+    from paper_1112_0065_amd import _lib as L
+    torch = torch_dev()
+    fbs = _beams(3)
+    plans = [L.dedisp_plan_create(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list) for fb in fbs]
+    ins = [to_dev(fb.packed) for fb in fbs]
+    outs = [torch.empty((p.ndm, fb.nsamps - p.max_delay), dtype=torch.int16, device="cuda")
+            for p, fb in zip(plans, fbs)]
+    evs = [torch.empty(4096 * 40, dtype=torch.uint8, device="cuda") for _ in fbs]
+    batch = L.dedisp_batch_create(plans, WIDTHS, 5.0)
+    ns = [fb.nsamps for fb in fbs]
+    first = None
+    for rep in range(4):
+        cnt = L.dedisp_batch_execute(batch, ins, ns, outs, evs, [4096] * 3)
+        snap = [o.clone() for o in outs] + [e.clone() for e in evs]
+        # eager work and a sync between replays
+        junk = torch.randn(1 << 20, device="cuda").sum().item()
+        assert np.isfinite(junk)
+        for o in outs:
+            o.fill_(0)
+        if first is None:
+            first = (cnt, snap)
+        else:
+            assert cnt == first[0]
+            assert all(torch.equal(a, b) for a, b in zip(snap, first[1]))
+    assert L.dedisp_batch_info(batch)[2] == 1
+    # shorter second beam: new capture, exact against the single-beam path
+    ns2 = list(ns)
+    ns2[1] = ns[1] - 3001
+    outs2 = list(outs)
+    outs2[1] = torch.empty((plans[1].ndm, ns2[1] - plans[1].max_delay), dtype=torch.int16,
+                           device="cuda")
+    L.dedisp_batch_execute(batch, ins, ns2, outs2, evs, [4096] * 3)
+    assert L.dedisp_batch_info(batch)[2] == 2
+    fb1 = fbs[1]
+    short = synth.Filterbank(fb1.name, fb1.seed, fb1.nchans, ns2[1], fb1.f_top, fb1.df, fb1.tsamp,
+                             fb1.dm_list, fb1.widths, fb1.snr_thresh,
+                             fb1.packed[: ns2[1] * fb1.nchans // 4], [])
+    s_out, _ = _single(plans[1], short, ins[1], torch.int16, torch, L)
+    assert torch.equal(outs2[1], s_out)
+
+
+def test_autotune_small_config(tmp_path):
+    from paper_1112_0065_amd import _lib as L
+    torch = torch_dev()
+    fb, dly, x, ref = small_case()
+    p = L.dedisp_plan_create(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list)
+    cache = str(tmp_path / "tune.json")
+    best, rejected = L.dedisp_autotune(p, fb.nsamps, True, cache)
+    log("autotune best", best, "rejected", rejected)
+    assert rejected == 0
+    assert best in L.dedisp_tile_candidates()
+    assert L.dedisp_default_tile(p) == best
+    entries = json.load(open(cache))
+    key = [k for k in entries if ":nchans=256:ndm=128:u16" in k]
+    assert key and entries[key[0]][:3] == list(best)
+    # a plan created with the cache in the environment starts from it
+    os.environ["DEDISP_TUNE_CACHE"] = cache
+    try:
+        p2 = L.dedisp_plan_create(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list)
+    finally:
+        del os.environ["DEDISP_TUNE_CACHE"]
+    assert L.dedisp_default_tile(p2) == best
+    out = torch.empty((p2.ndm, fb.nsamps - p2.max_delay), dtype=torch.int16, device="cuda")
+    ws = torch.empty(L.dedisp_workspace_bytes(p2, fb.nsamps), dtype=torch.uint8, device="cuda")
+    L.dedisp_execute(p2, to_dev(fb.packed), fb.nsamps, out, ws)
+    assert (out.cpu().numpy().view(np.uint16).astype(np.int64) == ref).all()
+    # batch reading the same cache uses the tuned shape
+    b = L.dedisp_batch_create([p2], WIDTHS, 5.0, tune_cache_path=cache)
+    assert L.dedisp_batch_info(b)[0] == best
