@@ -258,6 +258,88 @@ dedisp_status dedisp_autotune(dedisp_plan plan, int64_t nsamps, dedisp_out_type 
                               const char* cache_path, dedisp_tile* best_out,
                               int32_t* n_rejected);
 
+/* ------------------------------------------------------------------------
+ * Streaming server (the paper's aim: search in real time as the telescope
+ * observes, sections 1 and 3; 13 beams at ~4 MB/s each, section 1).
+ *
+ * Each beam delivers chunks of chunk_nsamps samples (packed as for
+ * dedisp_execute).  The server keeps on the device, per beam, the last
+ * H_b = max_delay_b + w_max - 1 input samples, so chunk k >= 1 of a beam
+ * (contiguous after chunk k-1) is searched over the window of absolute
+ * samples [k*C - H_b, (k+1)*C) and yields exactly C boxcar start positions;
+ * the first chunk of a beam, or the first after a gap in seq, yields C - H_b.
+ * The concatenated series / boxcars equal the one-shot result; the
+ * sigma-cut statistics are those of each chunk's positions.
+ *
+ * Admission: the overlaps are resident; the rest of hbm_budget_bytes is cut
+ * into chunk slots of dedisp_serve_slot_bytes() each (window, bit-planes,
+ * uint16 series, peak workspace, 65536 event records).  Continuous batching:
+ * whenever slots are free, every queued chunk of any beam joins the next
+ * persistent launch; copies of one batch overlap the compute of the previous
+ * one.  submit() copies the chunk to pinned staging and returns BUSY when the
+ * staging is full (the caller retries).  Chunks of a beam must be submitted
+ * in increasing seq; a smaller seq than already submitted is INVALID_ARG, a
+ * jump marks the result GAP.  arrival_ns is the caller's CLOCK_MONOTONIC time
+ * (steady clock) at which the chunk's last sample arrived; latency is
+ * done_ns - arrival_ns and LATE marks results later than C * tsamp.
+ * model: optional triage network (NULL: FALLBACK on every result, the plain
+ * S/N detector's events are returned unscored).
+ * poll(): up to cap results, waiting up to timeout_ms for the first; event
+ * arrays stay valid until the next poll.  destroy() drains queued work.
+ * ------------------------------------------------------------------------ */
+typedef struct dedisp_server_s* dedisp_server;
+typedef struct triage_model_s* triage_model;
+
+enum {
+    DEDISP_CHUNK_GAP = 1,       /* the chunk does not follow the previous one */
+    DEDISP_CHUNK_LATE = 2,      /* result later than the chunk duration       */
+    DEDISP_CHUNK_FALLBACK = 4,  /* no triage scores (no or invalid model)     */
+    DEDISP_CHUNK_OVERFLOW = 8   /* more than 65536 events: first 65536 kept   */
+};
+
+typedef struct {
+    int32_t beam;
+    int64_t seq;
+    int64_t t_abs0;        /* absolute sample index of the window start = first position */
+    int64_t n_bx;          /* boxcar start positions searched                            */
+    int64_t n_events;      /* events found (may exceed the records when OVERFLOW)        */
+    const dedisp_event* events;  /* host, min(n_events, 65536) records, t relative to t_abs0 */
+    const float* scores;   /* host, triage score per event, or NULL                        */
+    int64_t arrival_ns, done_ns;
+    int32_t flags;
+} dedisp_chunk_result;
+
+typedef struct {
+    int64_t chunks_done;
+    int64_t p50_ns, p99_ns, max_ns;   /* nearest-rank percentiles of latency */
+    int64_t deadline_ns;              /* C * tsamp                           */
+    int64_t deadline_misses;
+    int64_t batches, max_batch;
+    double mean_batch;
+    int32_t slots;
+} dedisp_serve_stats_t;
+
+size_t dedisp_serve_slot_bytes(const dedisp_plan* plans, int32_t nbeams, int64_t chunk_nsamps,
+                               const int32_t* widths, int32_t nwidths);
+dedisp_status dedisp_serve_create(const dedisp_plan* plans, int32_t nbeams, int64_t chunk_nsamps,
+                                  const int32_t* widths, int32_t nwidths, float snr_thresh,
+                                  size_t hbm_budget_bytes, triage_model model,
+                                  dedisp_server* out);
+dedisp_status dedisp_serve_submit(dedisp_server s, int32_t beam, int64_t seq,
+                                  const uint8_t* host_chunk, int64_t arrival_ns);
+dedisp_status dedisp_serve_poll(dedisp_server s, dedisp_chunk_result* out, int32_t cap,
+                                int32_t* n_out, int32_t timeout_ms);
+dedisp_status dedisp_serve_stats(dedisp_server s, dedisp_serve_stats_t* stats);
+dedisp_status dedisp_serve_destroy(dedisp_server s);
+/* Current time of the clock arrival_ns refers to. */
+int64_t dedisp_now_ns(void);
+/* Host-only helpers the server uses (no device needed):
+ * nearest-rank percentile q in (0,1] of an ascending array (0 when n <= 0);
+ * number of chunk slots a budget admits after the resident overlaps
+ * (0 when not even one fits; at most 4096). */
+int64_t dedisp_percentile_ns(const int64_t* sorted, int64_t n, double q);
+int32_t dedisp_serve_admission(size_t budget, size_t resident, size_t slot_bytes);
+
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* dedisp_last_error(void);
 

@@ -40,6 +40,22 @@ class _Tile(C.Structure):
     _fields_ = [("dms_per_block", C.c_int32), ("groups", C.c_int32), ("stage_chans", C.c_int32)]
 
 
+class _ChunkResult(C.Structure):
+    _fields_ = [("beam", C.c_int32), ("seq", C.c_int64), ("t_abs0", C.c_int64),
+                ("n_bx", C.c_int64), ("n_events", C.c_int64), ("events", C.c_void_p),
+                ("scores", C.POINTER(C.c_float)), ("arrival_ns", C.c_int64),
+                ("done_ns", C.c_int64), ("flags", C.c_int32)]
+
+
+class _ServeStats(C.Structure):
+    _fields_ = [("chunks_done", C.c_int64), ("p50_ns", C.c_int64), ("p99_ns", C.c_int64),
+                ("max_ns", C.c_int64), ("deadline_ns", C.c_int64),
+                ("deadline_misses", C.c_int64), ("batches", C.c_int64),
+                ("max_batch", C.c_int64), ("mean_batch", C.c_double), ("slots", C.c_int32)]
+
+
+CHUNK_GAP, CHUNK_LATE, CHUNK_FALLBACK, CHUNK_OVERFLOW = 1, 2, 4, 8
+
 _lib = None
 
 
@@ -80,6 +96,15 @@ def lib() -> C.CDLL:
         "dedisp_batch_info": (i32, [vp, P(_Tile), P(i32), P(i32)]),
         "dedisp_batch_destroy": (i32, [vp]),
         "dedisp_autotune": (i32, [vp, i64, i32, C.c_char_p, P(_Tile), P(i32)]),
+        "dedisp_serve_slot_bytes": (sz, [P(vp), i32, i64, P(i32), i32]),
+        "dedisp_serve_create": (i32, [P(vp), i32, i64, P(i32), i32, f32, sz, vp, P(vp)]),
+        "dedisp_serve_submit": (i32, [vp, i32, i64, vp, i64]),
+        "dedisp_serve_poll": (i32, [vp, P(_ChunkResult), i32, P(i32), i32]),
+        "dedisp_serve_stats": (i32, [vp, P(_ServeStats)]),
+        "dedisp_serve_destroy": (i32, [vp]),
+        "dedisp_now_ns": (i64, []),
+        "dedisp_percentile_ns": (i64, [P(i64), i64, f64]),
+        "dedisp_serve_admission": (i32, [sz, sz, sz]),
         "dedisp_last_error": (C.c_char_p, []),
         "dedisp_version": (C.c_char_p, []),
     }
@@ -351,3 +376,95 @@ def dedisp_autotune(plan: Plan, nsamps: int, out_u16: bool = True,
     _check(lib().dedisp_autotune(plan.handle, int(nsamps), OUT_U16 if out_u16 else OUT_I32, path,
                                  C.byref(t), C.byref(rej)))
     return (t.dms_per_block, t.groups, t.stage_chans), rej.value
+
+
+# ---------------------------------------------------------------------------
+# Streaming server
+# ---------------------------------------------------------------------------
+
+class Server:
+    def __init__(self, handle: int, plans, model=None):
+        self.handle = handle
+        self.plans = list(plans)
+        self.model = model
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            st = _lib.dedisp_serve_destroy(self.handle)
+            self.handle = None
+            _check(st)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dedisp_serve_slot_bytes(plans, chunk_nsamps: int, widths) -> int:
+    arr = (C.c_void_p * len(plans))(*[p.handle for p in plans])
+    return int(lib().dedisp_serve_slot_bytes(arr, len(plans), int(chunk_nsamps), _i32arr(widths),
+                                             len(widths)))
+
+
+def dedisp_serve_create(plans, chunk_nsamps: int, widths, snr_thresh: float, hbm_budget: int,
+                        model=None) -> Server:
+    arr = (C.c_void_p * len(plans))(*[p.handle for p in plans])
+    h = C.c_void_p()
+    mh = None if model is None else model.handle
+    _check(lib().dedisp_serve_create(arr, len(plans), int(chunk_nsamps), _i32arr(widths),
+                                     len(widths), float(snr_thresh), int(hbm_budget), mh,
+                                     C.byref(h)))
+    return Server(h.value, plans, model)
+
+
+def dedisp_serve_submit(server: Server, beam: int, seq: int, chunk: np.ndarray,
+                        arrival_ns: int) -> bool:
+    """True when admitted, False on BUSY (retry later)."""
+    buf = np.ascontiguousarray(chunk, dtype=np.uint8)
+    st = lib().dedisp_serve_submit(server.handle, int(beam), int(seq),
+                                   buf.ctypes.data_as(C.c_void_p), int(arrival_ns))
+    if st == ERR_BUSY:
+        return False
+    _check(st)
+    return True
+
+
+def dedisp_serve_poll(server: Server, cap: int = 64, timeout_ms: int = 0):
+    arr = (_ChunkResult * cap)()
+    n = C.c_int32()
+    _check(lib().dedisp_serve_poll(server.handle, arr, cap, C.byref(n), int(timeout_ms)))
+    out = []
+    for r in arr[: n.value]:
+        m = min(r.n_events, 1 << 16)
+        ev = np.empty(0, dtype=EVENT_DTYPE)
+        if m and r.events:
+            raw = C.string_at(r.events, m * EVENT_DTYPE.itemsize)
+            ev = np.frombuffer(raw, dtype=EVENT_DTYPE).copy()
+        scores = None
+        if m and r.scores:
+            scores = np.ctypeslib.as_array(r.scores, shape=(m,)).copy()
+        out.append(dict(beam=r.beam, seq=r.seq, t_abs0=r.t_abs0, n_bx=r.n_bx,
+                        n_events=r.n_events, events=ev, scores=scores,
+                        arrival_ns=r.arrival_ns, done_ns=r.done_ns, flags=r.flags))
+    return out
+
+
+def dedisp_serve_stats(server: Server) -> dict:
+    st = _ServeStats()
+    _check(lib().dedisp_serve_stats(server.handle, C.byref(st)))
+    return {k: getattr(st, k) for k, _ in _ServeStats._fields_}
+
+
+def dedisp_now_ns() -> int:
+    return int(lib().dedisp_now_ns())
+
+
+def dedisp_percentile_ns(values, q: float) -> int:
+    a = np.ascontiguousarray(np.sort(np.asarray(values, dtype=np.int64)))
+    return int(lib().dedisp_percentile_ns(a.ctypes.data_as(C.POINTER(C.c_int64)), len(a),
+                                          float(q)))
+
+
+def dedisp_serve_admission(budget: int, resident: int, slot_bytes: int) -> int:
+    return int(lib().dedisp_serve_admission(int(budget), int(resident), int(slot_bytes)))

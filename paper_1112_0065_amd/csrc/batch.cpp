@@ -30,6 +30,7 @@ struct dedisp_batch_s {
     dd::BeamArgs* d_beams = nullptr;
     unsigned long long* d_counters = nullptr;
     int64_t* h_totals = nullptr;   // pinned
+    dd::BeamArgs* h_beams = nullptr;   // pinned descriptor staging
     std::vector<void*> words, pk_ws;
     std::vector<size_t> words_bytes, pk_bytes;
     hipStream_t cap = nullptr;
@@ -38,14 +39,58 @@ struct dedisp_batch_s {
     // capture key
     std::vector<const void*> k_in, k_out, k_ev;
     std::vector<int64_t> k_nsamps, k_cap;
-    int64_t total_items = 0;
     int captures = 0;
 };
 
 namespace dd {
-dedisp_status split_threshold_public(float k, uint32_t* kmant, int* kexp2);
-dedisp_status check_widths_public(const int32_t* widths, int32_t nwidths, int64_t nout, Widths* W);
-TileConfig tuned_or_default(const dedisp_plan_s* p, const char* cache_path, int out_u16);
+
+// Enqueue on `s`: descriptor upload (from pinned h_beams), repack of every
+// item, one persistent dedispersion over all items, then each item's
+// boxcar / sigma-cut / peak chain and the D2H copy of its event count.
+hipError_t launch_multi(const MultiItem* items, int n, const Widths& W, uint32_t kmant, int kexp2,
+                        int out_u16, const TileConfig& cfg, int nl, size_t lds, int grid, int nq,
+                        BeamArgs* h_beams, BeamArgs* d_beams, unsigned long long* d_counters,
+                        hipStream_t s) {
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        const MultiItem& it = items[i];
+        const int64_t nout = it.nsamps - it.plan->max_delay;
+        h_beams[i] = beam_args(it.plan, static_cast<const uint2*>(it.words), repack_words(it.nsamps),
+                               nout, it.out, cfg);
+        h_beams[i].item_begin = total;
+        total += h_beams[i].n_items;
+    }
+    hipError_t e = hipMemcpyAsync(d_beams, h_beams, sizeof(BeamArgs) * n, hipMemcpyHostToDevice, s);
+    for (int i = 0; i < n && e == hipSuccess; ++i)
+        e = launch_repack(items[i].in, items[i].nsamps, items[i].plan->nchans,
+                          static_cast<uint2*>(items[i].words), repack_words(items[i].nsamps), s);
+    if (e == hipSuccess)
+        e = launch_dedisperse_persistent(d_beams, n, total, nl, out_u16, cfg, lds, d_counters, nq,
+                                         grid, s);
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        const MultiItem& it = items[i];
+        const dedisp_plan_s* p = it.plan;
+        const int64_t nout = it.nsamps - p->max_delay;
+        const PeaksLayout lay = peaks_layout(p->ndm, nout, W);
+        const PeaksWs ws = peaks_ws(it.pk_ws, lay);
+        e = launch_peaks_count(it.out, out_u16, p->ndm, nout, W, lay, ws, kmant, kexp2, s);
+        if (e == hipSuccess && it.capacity > 0)
+            e = launch_peaks_write(it.out, out_u16, p->ndm, nout, W, lay, ws, it.events, it.capacity, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(it.h_total, ws.total, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    }
+    return e;
+}
+
+int batch_grid(int nl, int out_u16, const TileConfig& cfg, size_t lds, int device, int nq) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return 0;
+    const int per_cu = persistent_blocks_per_cu(nl, out_u16, cfg, lds);
+    if (cus < 1 || per_cu < 1) return 0;
+    return ((cus * per_cu + nq - 1) / nq) * nq;
+}
+
 }  // namespace dd
 
 namespace {
@@ -112,14 +157,12 @@ extern "C" dedisp_status dedisp_batch_create(const dedisp_plan* plans, int32_t n
         delete b;
         return fail(DEDISP_ERR_UNSUPPORTED, "LDS tile of %zu bytes too large", b->lds);
     }
-    int cus = 0;
-    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, plans[0]->device);
-    const int per_cu = dd::persistent_blocks_per_cu(nl, b->out_u16, b->cfg, b->lds);
-    if (e != hipSuccess || cus < 1 || per_cu < 1) {
+    b->grid = dd::batch_grid(nl, b->out_u16, b->cfg, b->lds, plans[0]->device, b->nq);
+    if (b->grid < 1) {
         delete b;
-        return fail(DEDISP_ERR_HIP, "occupancy query failed (%d CUs, %d blocks per CU)", cus, per_cu);
+        return fail(DEDISP_ERR_HIP, "occupancy query of the persistent kernel failed");
     }
-    b->grid = ((cus * per_cu + b->nq - 1) / b->nq) * b->nq;
+    hipError_t e = hipSuccess;
     b->words.assign(nbeams, nullptr);
     b->pk_ws.assign(nbeams, nullptr);
     b->words_bytes.assign(nbeams, 0);
@@ -127,6 +170,8 @@ extern "C" dedisp_status dedisp_batch_create(const dedisp_plan* plans, int32_t n
     e = hipMalloc(&b->d_beams, sizeof(dd::BeamArgs) * nbeams);
     if (e == hipSuccess) e = hipMalloc(&b->d_counters, sizeof(unsigned long long) * b->nq);
     if (e == hipSuccess) e = hipHostMalloc(&b->h_totals, sizeof(int64_t) * nbeams, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc(&b->h_beams, sizeof(dd::BeamArgs) * nbeams, hipHostMallocDefault);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
         dedisp_batch_destroy(b);
@@ -147,6 +192,7 @@ extern "C" dedisp_status dedisp_batch_destroy(dedisp_batch b) {
     if (b->d_beams) (void)hipFree(b->d_beams);
     if (b->d_counters) (void)hipFree(b->d_counters);
     if (b->h_totals) (void)hipHostFree(b->h_totals);
+    if (b->h_beams) (void)hipHostFree(b->h_beams);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     delete b;
     return DEDISP_OK;
@@ -166,42 +212,14 @@ namespace {
 dedisp_status capture(dedisp_batch_s* b, const uint8_t* const* in, const int64_t* nsamps,
                       void* const* out, dedisp_event* const* events, const int64_t* capacity) {
     release_graph(b);
-    // Per-beam descriptors, item ranges laid end to end.
-    std::vector<dd::BeamArgs> args(b->nbeams);
-    int64_t total = 0;
-    for (int i = 0; i < b->nbeams; ++i) {
-        const dedisp_plan_s* p = b->plans[i];
-        const int64_t nout = nsamps[i] - p->max_delay;
-        args[i] = dd::beam_args(p, static_cast<const uint2*>(b->words[i]), dd::repack_words(nsamps[i]),
-                                nout, out[i], b->cfg);
-        args[i].item_begin = total;
-        total += args[i].n_items;
-    }
-    b->total_items = total;
-    DD_HIP(hipMemcpy(b->d_beams, args.data(), sizeof(dd::BeamArgs) * b->nbeams, hipMemcpyHostToDevice));
-
+    std::vector<dd::MultiItem> items(b->nbeams);
+    for (int i = 0; i < b->nbeams; ++i)
+        items[i] = dd::MultiItem{b->plans[i], in[i], nsamps[i], b->words[i], out[i], b->pk_ws[i],
+                                 events[i], capacity[i], &b->h_totals[i]};
     DD_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
-    for (int i = 0; i < b->nbeams && e == hipSuccess; ++i)
-        e = dd::launch_repack(in[i], nsamps[i], b->plans[i]->nchans, static_cast<uint2*>(b->words[i]),
-                              dd::repack_words(nsamps[i]), b->cap);
-    if (e == hipSuccess)
-        e = dd::launch_dedisperse_persistent(b->d_beams, b->nbeams, total, b->nl, b->out_u16, b->cfg,
-                                             b->lds, b->d_counters, b->nq, b->grid, b->cap);
-    for (int i = 0; i < b->nbeams && e == hipSuccess; ++i) {
-        const dedisp_plan_s* p = b->plans[i];
-        const int64_t nout = nsamps[i] - p->max_delay;
-        const dd::PeaksLayout lay = dd::peaks_layout(p->ndm, nout, b->W);
-        const dd::PeaksWs ws = dd::peaks_ws(b->pk_ws[i], lay);
-        e = dd::launch_peaks_count(out[i], b->out_u16, p->ndm, nout, b->W, lay, ws, b->kmant,
-                                   b->kexp2, b->cap);
-        if (e == hipSuccess && capacity[i] > 0)
-            e = dd::launch_peaks_write(out[i], b->out_u16, p->ndm, nout, b->W, lay, ws, events[i],
-                                       capacity[i], b->cap);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(&b->h_totals[i], ws.total, sizeof(int64_t), hipMemcpyDeviceToHost,
-                               b->cap);
-    }
+    const hipError_t e = dd::launch_multi(items.data(), b->nbeams, b->W, b->kmant, b->kexp2, b->out_u16,
+                                          b->cfg, b->nl, b->lds, b->grid, b->nq, b->h_beams, b->d_beams,
+                                          b->d_counters, b->cap);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(b->cap, &g);
     if (e != hipSuccess || e2 != hipSuccess) {

@@ -101,6 +101,20 @@ hipError_t launch_dedisperse_persistent(const BeamArgs* d_beams, int nbeams, int
                                         int nl, int out_u16, const TileConfig& cfg, size_t lds,
                                         unsigned long long* d_counters, int nq, int grid,
                                         hipStream_t s);
+// One beam (or one streamed window) of a multi-item run.
+struct MultiItem {
+    const dedisp_plan_s* plan;
+    const uint8_t* in;      // device, packed 2-bit input
+    int64_t nsamps;
+    void* words;            // device, bit-plane workspace
+    void* out;              // device series [ndm][nsamps - max_delay]
+    void* pk_ws;            // device find_peaks workspace
+    dedisp_event* events;   // device, capacity records
+    int64_t capacity;
+    int64_t* h_total;       // pinned host: number of events found
+};
+// Persistent grid size for this shape on `device` (multiple of nq; 0 on error).
+int batch_grid(int nl, int out_u16, const TileConfig& cfg, size_t lds, int device, int nq);
 // Resident blocks per CU of the persistent kernel for this shape (0 on error).
 int persistent_blocks_per_cu(int nl, int out_u16, const TileConfig& cfg, size_t lds);
 

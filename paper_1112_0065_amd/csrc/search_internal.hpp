@@ -7,6 +7,7 @@
 #include <cstdint>
 
 #include "../../include/dedisp.h"
+#include "dedisp_internal.hpp"
 
 namespace dd {
 
@@ -60,5 +61,14 @@ hipError_t launch_peaks_count(const void* in, int in_u16, int ndm, int64_t nout,
 hipError_t launch_peaks_write(const void* in, int in_u16, int ndm, int64_t nout, const Widths& W,
                               const PeaksLayout& lay, const PeaksWs& ws, dedisp_event* events,
                               int64_t capacity, hipStream_t s);
+
+// Shared by the batch and the streaming server: see batch.cpp.
+hipError_t launch_multi(const MultiItem* items, int n, const Widths& W, uint32_t kmant, int kexp2,
+                        int out_u16, const TileConfig& cfg, int nl, size_t lds, int grid, int nq,
+                        BeamArgs* h_beams, BeamArgs* d_beams, unsigned long long* d_counters,
+                        hipStream_t s);
+dedisp_status split_threshold_public(float k, uint32_t* kmant, int* kexp2);
+dedisp_status check_widths_public(const int32_t* widths, int32_t nwidths, int64_t nout, Widths* W);
+TileConfig tuned_or_default(const dedisp_plan_s* p, const char* cache_path, int out_u16);
 
 }  // namespace dd

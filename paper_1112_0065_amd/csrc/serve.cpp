@@ -1,0 +1,589 @@
+// Streaming server: real-time search of every beam's chunks as they arrive.
+//
+// The paper's goal is detection in real time, as the telescope observes
+// (sections 1 and 3), with the 13 beams of the multibeam receiver (section 1)
+// arriving continuously at about 4 MB/s each.  This engine takes each beam's
+// chunks of C samples, keeps on the device the last H = max_delay + w_max - 1
+// input samples of every beam (the overlap the next chunk's dedispersion and
+// widest boxcar need), admits chunks into device slots sized against an HBM
+// budget, and continuously batches: whenever slots are free, every queued
+// chunk of any beam joins the next persistent launch, while the copies of
+// that batch overlap the compute of the previous one (separate streams).
+//
+// Chunk k >= 1 of a beam (contiguous after chunk k-1) is searched over the
+// window of absolute samples [kC - H, (k+1)C), giving exactly C boxcar start
+// positions; the first chunk of a beam (or the first after a gap) has no
+// overlap and gives C - H positions.  The concatenated integer results equal
+// the one-shot result.  Statistics of the sigma-cut are those of each chunk.
+//
+// Threads: callers (submit / poll), one scheduler (assembles and launches
+// batches), one completion thread (waits for a batch, copies events back,
+// records latency, frees slots).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "dedisp_internal.hpp"
+#include "search_internal.hpp"
+#include "triage_internal.hpp"
+
+using dd::fail;
+
+extern "C" int64_t dedisp_percentile_ns(const int64_t* sorted, int64_t n, double q);
+extern "C" int32_t dedisp_serve_admission(size_t budget, size_t resident, size_t slot_bytes);
+
+namespace {
+
+int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct Slot {
+    uint8_t* window = nullptr;    // packed input window (H + C samples max)
+    void* words = nullptr;        // bit-plane workspace
+    void* out = nullptr;          // uint16 series
+    void* pk_ws = nullptr;        // find_peaks workspace
+    dedisp_event* d_events = nullptr;
+    bool busy = false;
+};
+
+struct Job {
+    int beam = 0;
+    int64_t seq = 0;
+    int64_t arrival_ns = 0;
+    int32_t flags = 0;
+    int host_buf = -1;       // index of the pinned staging buffer
+    int slot = -1;
+    int64_t t_abs0 = 0;      // absolute sample index of the window start
+    int64_t nsamps = 0;      // window length
+    bool overlap = false;
+    int64_t* h_total = nullptr;
+};
+
+struct Batch {
+    std::vector<Job> jobs;
+    hipEvent_t done = nullptr;
+    int ring = 0;
+};
+
+struct Result {
+    dedisp_chunk_result r;
+    std::vector<dedisp_event> events;
+    std::vector<float> scores;
+};
+
+}  // namespace
+
+struct dedisp_server_s {
+    std::vector<dedisp_plan> plans;
+    int nbeams = 0;
+    int64_t C = 0;
+    int64_t H = 0;                 // max over beams of max_delay + w_max - 1
+    std::vector<int64_t> Hb;       // per beam
+    int nchans = 0;
+    dd::Widths W{};
+    uint32_t kmant = 0;
+    int kexp2 = 0;
+    dd::TileConfig cfg{};
+    int nl = 12;
+    size_t lds = 0;
+    int grid = 0;
+    int nq = 8;
+    int64_t capacity = 1 << 16;
+    triage_model model = nullptr;
+    float triage_thresh = 0.5f;
+    double deadline_ns = 0;
+
+    // device
+    std::vector<uint8_t*> overlap;       // per beam, H_b samples of packed input
+    std::vector<Slot> slots;
+    static constexpr int kRing = 4;      // batches in flight
+    dd::BeamArgs* h_beams[kRing] = {};
+    dd::BeamArgs* d_beams[kRing] = {};
+    unsigned long long* d_counters = nullptr;
+    int64_t* h_totals = nullptr;         // pinned, one per slot
+    std::vector<uint8_t*> host_bufs;     // pinned chunk staging
+    std::vector<bool> host_busy;
+    hipStream_t copy_s = nullptr, comp_s = nullptr, done_s = nullptr;
+
+    // per-beam stream state (scheduler side)
+    std::vector<int64_t> next_seq;       // expected next sequence number (submit side)
+    std::vector<bool> have_overlap;
+
+    // queues
+    std::mutex mu;
+    std::condition_variable cv_sched, cv_done, cv_poll;
+    std::deque<Job> pending;
+    std::deque<Batch> inflight;
+    std::deque<Result> results;
+    std::vector<Result> last_polled;
+    bool stop = false;
+    int ring_next = 0;
+    int ring_used = 0;
+    dedisp_status async_error = DEDISP_OK;
+    std::string async_msg;
+
+    // statistics
+    std::vector<int64_t> latencies;
+    int64_t batches = 0, batched_chunks = 0, misses = 0, max_batch = 0;
+
+    std::thread sched, compl_;
+};
+
+namespace {
+
+void set_async_error(dedisp_server_s* s, dedisp_status st, const char* what, hipError_t e) {
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->async_error == DEDISP_OK) {
+        s->async_error = st;
+        s->async_msg = std::string(what) + ": " + hipGetErrorString(e);
+    }
+    s->stop = true;
+    s->cv_poll.notify_all();
+    s->cv_sched.notify_all();
+    s->cv_done.notify_all();
+}
+
+// Assemble one job's window on copy_s: [overlap | chunk], then save the new
+// overlap.  Runs in the scheduler thread in per-beam sequence order.
+hipError_t assemble(dedisp_server_s* s, Job& j) {
+    const int64_t bpc = s->nchans / 4;   // bytes per sample
+    const int64_t Hb = s->Hb[j.beam];
+    Slot& sl = s->slots[j.slot];
+    hipError_t e = hipSuccess;
+    int64_t off = 0;
+    if (j.overlap) {
+        e = hipMemcpyAsync(sl.window, s->overlap[j.beam], Hb * bpc, hipMemcpyDeviceToDevice, s->copy_s);
+        off = Hb;
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sl.window + off * bpc, s->host_bufs[j.host_buf], s->C * bpc,
+                           hipMemcpyHostToDevice, s->copy_s);
+    j.nsamps = off + s->C;
+    // new overlap: the window's last H_b samples
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->overlap[j.beam], sl.window + (j.nsamps - Hb) * bpc, Hb * bpc,
+                           hipMemcpyDeviceToDevice, s->copy_s);
+    return e;
+}
+
+void scheduler(dedisp_server_s* s) {
+    hipSetDevice(s->plans[0]->device);
+    hipEvent_t copied = nullptr;
+    if (hipEventCreateWithFlags(&copied, hipEventDisableTiming) != hipSuccess) return;
+    for (;;) {
+        std::vector<Job> take;
+        int ring = 0;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_sched.wait(lk, [&] {
+                if (s->stop) return true;
+                if (s->pending.empty() || s->ring_used >= dedisp_server_s::kRing) return false;
+                for (const Slot& sl : s->slots)
+                    if (!sl.busy) return true;
+                return false;
+            });
+            if (s->stop) break;
+            // every pending chunk (any beam, in arrival order) while slots last
+            for (size_t i = 0; i < s->slots.size() && !s->pending.empty(); ++i) {
+                if (s->slots[i].busy) continue;
+                Job j = s->pending.front();
+                s->pending.pop_front();
+                s->slots[i].busy = true;
+                j.slot = static_cast<int>(i);
+                j.h_total = &s->h_totals[i];
+                // overlap bookkeeping in sequence order
+                j.overlap = s->have_overlap[j.beam] && !(j.flags & DEDISP_CHUNK_GAP);
+                j.t_abs0 = j.seq * s->C - (j.overlap ? s->Hb[j.beam] : 0);
+                s->have_overlap[j.beam] = true;
+                take.push_back(j);
+            }
+            ring = s->ring_next;
+            s->ring_next = (s->ring_next + 1) % dedisp_server_s::kRing;
+            s->ring_used++;
+        }
+        hipError_t e = hipSuccess;
+        for (Job& j : take)
+            if (e == hipSuccess) e = assemble(s, j);
+        if (e == hipSuccess) e = hipEventRecord(copied, s->copy_s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s->comp_s, copied, 0);
+        std::vector<dd::MultiItem> items(take.size());
+        for (size_t i = 0; i < take.size(); ++i) {
+            const Slot& sl = s->slots[take[i].slot];
+            items[i] = dd::MultiItem{s->plans[take[i].beam], sl.window, take[i].nsamps, sl.words, sl.out,
+                                     sl.pk_ws, sl.d_events, s->capacity, take[i].h_total};
+        }
+        if (e == hipSuccess)
+            e = dd::launch_multi(items.data(), static_cast<int>(items.size()), s->W, s->kmant, s->kexp2, 1,
+                                 s->cfg, s->nl, s->lds, s->grid, s->nq, s->h_beams[ring],
+                                 s->d_beams[ring], s->d_counters, s->comp_s);
+        Batch b;
+        b.jobs = std::move(take);
+        b.ring = ring;
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(b.done, s->comp_s);
+        if (e != hipSuccess) {
+            set_async_error(s, DEDISP_ERR_HIP, "batch launch", e);
+            break;
+        }
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            s->inflight.push_back(std::move(b));
+            s->batches++;
+            s->batched_chunks += static_cast<int64_t>(s->inflight.back().jobs.size());
+            s->max_batch = std::max<int64_t>(s->max_batch, s->inflight.back().jobs.size());
+        }
+        s->cv_done.notify_one();
+    }
+    (void)hipEventDestroy(copied);
+}
+
+void completer(dedisp_server_s* s) {
+    hipSetDevice(s->plans[0]->device);
+    for (;;) {
+        Batch b;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_done.wait(lk, [&] { return s->stop || !s->inflight.empty(); });
+            if (s->inflight.empty()) break;   // stop requested and nothing left
+            b = std::move(s->inflight.front());
+            s->inflight.pop_front();
+        }
+        hipError_t e = hipEventSynchronize(b.done);
+        (void)hipEventDestroy(b.done);
+        std::vector<Result> done;
+        for (Job& j : b.jobs) {
+            Result r{};
+            const int64_t n = e == hipSuccess ? *j.h_total : 0;
+            const int64_t m = std::min(n, s->capacity);
+            r.events.resize(static_cast<size_t>(m));
+            if (e == hipSuccess && m > 0)
+                e = hipMemcpyAsync(r.events.data(), s->slots[j.slot].d_events, m * sizeof(dedisp_event),
+                                   hipMemcpyDeviceToHost, s->done_s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s->done_s);
+            int32_t flags = j.flags;
+            if (n > s->capacity) flags |= DEDISP_CHUNK_OVERFLOW;
+            if (e == hipSuccess && s->model) {
+                const dedisp_plan_s* p = s->plans[j.beam];
+                const int64_t nout = j.nsamps - p->max_delay;
+                dedisp_status tst = dd::triage_score_events(s->model, s->slots[j.slot].out, p->ndm, nout,
+                                                            s->W, r.events.data(), m, &r.scores,
+                                                            s->done_s);
+                if (tst != DEDISP_OK) flags |= DEDISP_CHUNK_FALLBACK;
+            } else if (!s->model) {
+                flags |= DEDISP_CHUNK_FALLBACK;
+            }
+            r.r.beam = j.beam;
+            r.r.seq = j.seq;
+            r.r.t_abs0 = j.t_abs0;
+            r.r.n_bx = j.nsamps - s->plans[j.beam]->max_delay - s->W.w[s->W.n - 1] + 1;
+            r.r.n_events = n;
+            r.r.arrival_ns = j.arrival_ns;
+            r.r.done_ns = now_ns();
+            if (r.r.done_ns - j.arrival_ns > s->deadline_ns) flags |= DEDISP_CHUNK_LATE;
+            r.r.flags = flags;
+            done.push_back(std::move(r));
+        }
+        if (e != hipSuccess) {
+            set_async_error(s, DEDISP_ERR_HIP, "batch completion", e);
+            break;
+        }
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            for (Job& j : b.jobs) {
+                s->slots[j.slot].busy = false;
+                s->host_busy[j.host_buf] = false;
+            }
+            s->ring_used--;
+            for (Result& r : done) {
+                s->latencies.push_back(r.r.done_ns - r.r.arrival_ns);
+                if (r.r.flags & DEDISP_CHUNK_LATE) s->misses++;
+                s->results.push_back(std::move(r));
+            }
+        }
+        s->cv_sched.notify_one();
+        s->cv_poll.notify_all();
+    }
+}
+
+void free_server(dedisp_server_s* s) {
+    for (uint8_t* p : s->overlap)
+        if (p) (void)hipFree(p);
+    for (Slot& sl : s->slots) {
+        if (sl.window) (void)hipFree(sl.window);
+        if (sl.words) (void)hipFree(sl.words);
+        if (sl.out) (void)hipFree(sl.out);
+        if (sl.pk_ws) (void)hipFree(sl.pk_ws);
+        if (sl.d_events) (void)hipFree(sl.d_events);
+    }
+    for (int i = 0; i < dedisp_server_s::kRing; ++i) {
+        if (s->h_beams[i]) (void)hipHostFree(s->h_beams[i]);
+        if (s->d_beams[i]) (void)hipFree(s->d_beams[i]);
+    }
+    if (s->d_counters) (void)hipFree(s->d_counters);
+    if (s->h_totals) (void)hipHostFree(s->h_totals);
+    for (uint8_t* p : s->host_bufs)
+        if (p) (void)hipHostFree(p);
+    if (s->copy_s) (void)hipStreamDestroy(s->copy_s);
+    if (s->comp_s) (void)hipStreamDestroy(s->comp_s);
+    if (s->done_s) (void)hipStreamDestroy(s->done_s);
+    delete s;
+}
+
+}  // namespace
+
+extern "C" int64_t dedisp_now_ns(void) { return now_ns(); }
+
+extern "C" int64_t dedisp_percentile_ns(const int64_t* sorted, int64_t n, double q) {
+    // nearest-rank percentile of an ascending array
+    if (!sorted || n <= 0) return 0;
+    int64_t k = static_cast<int64_t>(std::ceil(q * static_cast<double>(n) - 1e-9));
+    k = std::max<int64_t>(1, std::min<int64_t>(k, n));
+    return sorted[k - 1];
+}
+
+extern "C" int32_t dedisp_serve_admission(size_t budget, size_t resident, size_t slot_bytes) {
+    if (slot_bytes == 0 || budget < resident + slot_bytes) return 0;
+    return static_cast<int32_t>(std::min<size_t>(4096, (budget - resident) / slot_bytes));
+}
+
+extern "C" size_t dedisp_serve_slot_bytes(const dedisp_plan* plans, int32_t nbeams,
+                                          int64_t chunk_nsamps, const int32_t* widths,
+                                          int32_t nwidths) {
+    if (!plans || nbeams < 1 || chunk_nsamps < 1 || !widths || nwidths < 1) return 0;
+    int64_t H = 0, ndm = 0, nchans = 0;
+    const int w_max = widths[nwidths - 1];
+    for (int b = 0; b < nbeams; ++b) {
+        if (!plans[b]) return 0;
+        H = std::max<int64_t>(H, plans[b]->max_delay + w_max - 1);
+        ndm = std::max<int64_t>(ndm, plans[b]->ndm);
+        nchans = std::max<int64_t>(nchans, plans[b]->nchans);
+    }
+    const int64_t win = H + chunk_nsamps;
+    dd::Widths W;
+    if (dd::check_widths_public(widths, nwidths, chunk_nsamps + w_max - 1, &W) != DEDISP_OK) return 0;
+    const size_t a = static_cast<size_t>(win * nchans / 4);
+    const size_t b = static_cast<size_t>(nchans) * dd::repack_words(win) * sizeof(uint2);
+    const size_t c = static_cast<size_t>(ndm) * (chunk_nsamps + w_max - 1) * 2;
+    const size_t d = dd::peaks_layout(static_cast<int>(ndm), chunk_nsamps + w_max - 1, W).bytes;
+    const size_t e = static_cast<size_t>(1 << 16) * sizeof(dedisp_event);
+    return a + b + c + d + e;
+}
+
+extern "C" dedisp_status dedisp_serve_create(const dedisp_plan* plans, int32_t nbeams,
+                                             int64_t chunk_nsamps, const int32_t* widths,
+                                             int32_t nwidths, float snr_thresh,
+                                             size_t hbm_budget_bytes, triage_model model,
+                                             dedisp_server* out) {
+    if (!out || !plans || nbeams < 1 || nbeams > 1024 || chunk_nsamps < 64)
+        return fail(DEDISP_ERR_INVALID_ARG, "need plans, 1..1024 beams, chunk of >= 64 samples");
+    *out = nullptr;
+    const int nchans = plans[0] ? plans[0]->nchans : 0;
+    for (int b = 0; b < nbeams; ++b) {
+        if (!plans[b]) return fail(DEDISP_ERR_INVALID_ARG, "plan %d is NULL", b);
+        if (plans[b]->nchans != nchans)
+            return fail(DEDISP_ERR_UNSUPPORTED, "all beams need the same channel count");
+        if (plans[b]->device != plans[0]->device)
+            return fail(DEDISP_ERR_INVALID_ARG, "all plans must be on one device");
+    }
+    dd::Widths W;
+    dedisp_status st = dd::check_widths_public(widths, nwidths, INT64_C(1) << 30, &W);
+    if (st != DEDISP_OK) return st;
+    uint32_t km;
+    int ke;
+    st = dd::split_threshold_public(snr_thresh, &km, &ke);
+    if (st != DEDISP_OK) return st;
+    dedisp_server_s* s = new (std::nothrow) dedisp_server_s;
+    if (!s) return fail(DEDISP_ERR_OUT_OF_MEMORY, "host allocation failed");
+    s->plans.assign(plans, plans + nbeams);
+    s->nbeams = nbeams;
+    s->C = chunk_nsamps;
+    s->nchans = nchans;
+    s->W = W;
+    s->kmant = km;
+    s->kexp2 = ke;
+    s->model = model;
+    const int w_max = W.w[W.n - 1];
+    for (int b = 0; b < nbeams; ++b) {
+        s->Hb.push_back(plans[b]->max_delay + w_max - 1);
+        s->H = std::max(s->H, s->Hb.back());
+    }
+    if (s->C <= s->H) {
+        delete s;
+        return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "chunk of %lld samples <= overlap %lld",
+                    static_cast<long long>(chunk_nsamps), static_cast<long long>(s->H));
+    }
+    s->deadline_ns = static_cast<double>(s->C) * plans[0]->tsamp * 1e9;
+    s->nl = dd::levels_for(nchans);
+    s->cfg = dd::default_tile_config(plans[0]);
+    for (int b = 0; b < nbeams; ++b) s->lds = std::max(s->lds, dd::tile_lds_bytes(plans[b], s->cfg));
+    s->grid = dd::batch_grid(s->nl, 1, s->cfg, s->lds, plans[0]->device, s->nq);
+    if (s->lds > 160 * 1024 || s->grid < 1) {
+        delete s;
+        return fail(DEDISP_ERR_UNSUPPORTED, "tile shape does not fit (LDS %zu bytes)", s->lds);
+    }
+    // HBM admission: resident overlaps first, then as many chunk slots as fit.
+    const size_t slot_bytes = dedisp_serve_slot_bytes(plans, nbeams, chunk_nsamps, widths, nwidths);
+    size_t resident = 0;
+    for (int b = 0; b < nbeams; ++b) resident += static_cast<size_t>(s->Hb[b] * nchans / 4);
+    const int nslots = dedisp_serve_admission(hbm_budget_bytes, resident, slot_bytes);
+    if (nslots < 1) {
+        delete s;
+        return fail(DEDISP_ERR_OUT_OF_MEMORY,
+                    "HBM budget %zu bytes below overlap (%zu) + one chunk slot (%zu)",
+                    hbm_budget_bytes, resident, slot_bytes);
+    }
+    hipError_t e = hipSuccess;
+    const int64_t win = s->H + s->C;
+    int64_t ndm_max = 0;
+    for (int b = 0; b < nbeams; ++b) ndm_max = std::max<int64_t>(ndm_max, plans[b]->ndm);
+    s->overlap.assign(nbeams, nullptr);
+    for (int b = 0; b < nbeams && e == hipSuccess; ++b)
+        e = hipMalloc(&s->overlap[b], static_cast<size_t>(s->Hb[b] * nchans / 4));
+    s->slots.resize(nslots);
+    for (int i = 0; i < nslots && e == hipSuccess; ++i) {
+        Slot& sl = s->slots[i];
+        e = hipMalloc(&sl.window, static_cast<size_t>(win * nchans / 4));
+        if (e == hipSuccess) e = hipMalloc(&sl.words, static_cast<size_t>(nchans) * dd::repack_words(win) * sizeof(uint2));
+        if (e == hipSuccess) e = hipMalloc(&sl.out, static_cast<size_t>(ndm_max) * (s->C + w_max - 1) * 2);
+        if (e == hipSuccess)
+            e = hipMalloc(&sl.pk_ws, dd::peaks_layout(static_cast<int>(ndm_max), s->C + w_max - 1, W).bytes);
+        if (e == hipSuccess) e = hipMalloc(&sl.d_events, static_cast<size_t>(s->capacity) * sizeof(dedisp_event));
+    }
+    for (int i = 0; i < dedisp_server_s::kRing && e == hipSuccess; ++i) {
+        e = hipHostMalloc(&s->h_beams[i], sizeof(dd::BeamArgs) * nslots, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc(&s->d_beams[i], sizeof(dd::BeamArgs) * nslots);
+    }
+    if (e == hipSuccess) e = hipMalloc(&s->d_counters, sizeof(unsigned long long) * s->nq);
+    if (e == hipSuccess) e = hipHostMalloc(&s->h_totals, sizeof(int64_t) * nslots, hipHostMallocDefault);
+    const int nhost = 2 * nslots + nbeams;
+    s->host_bufs.assign(nhost, nullptr);
+    s->host_busy.assign(nhost, false);
+    for (int i = 0; i < nhost && e == hipSuccess; ++i)
+        e = hipHostMalloc(&s->host_bufs[i], static_cast<size_t>(s->C * nchans / 4), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy_s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->comp_s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->done_s, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        free_server(s);
+        return fail(e == hipErrorOutOfMemory ? DEDISP_ERR_OUT_OF_MEMORY : DEDISP_ERR_HIP,
+                    "server setup: %s", hipGetErrorString(e));
+    }
+    s->next_seq.assign(nbeams, -1);
+    s->have_overlap.assign(nbeams, false);
+    s->sched = std::thread(scheduler, s);
+    s->compl_ = std::thread(completer, s);
+    *out = s;
+    dd::clear_error();
+    return DEDISP_OK;
+}
+
+extern "C" dedisp_status dedisp_serve_submit(dedisp_server s, int32_t beam, int64_t seq,
+                                             const uint8_t* host_chunk, int64_t arrival_ns) {
+    if (!s || !host_chunk || beam < 0 || beam >= s->nbeams || seq < 0)
+        return fail(DEDISP_ERR_INVALID_ARG, "bad submit arguments");
+    int hb = -1;
+    int32_t flags = 0;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        if (s->async_error != DEDISP_OK) return fail(s->async_error, "%s", s->async_msg.c_str());
+        const int64_t expect = s->next_seq[beam];
+        if (expect >= 0 && seq < expect)
+            return fail(DEDISP_ERR_INVALID_ARG, "beam %d: chunk %lld arrives after chunk %lld", beam,
+                        static_cast<long long>(seq), static_cast<long long>(expect - 1));
+        for (size_t i = 0; i < s->host_busy.size(); ++i)
+            if (!s->host_busy[i]) {
+                hb = static_cast<int>(i);
+                break;
+            }
+        if (hb < 0) return DEDISP_ERR_BUSY;   // back-pressure: not admitted yet
+        s->host_busy[hb] = true;
+        if (expect >= 0 && seq > expect) flags |= DEDISP_CHUNK_GAP;
+        s->next_seq[beam] = seq + 1;
+    }
+    std::memcpy(s->host_bufs[hb], host_chunk, static_cast<size_t>(s->C * s->nchans / 4));
+    Job j;
+    j.beam = beam;
+    j.seq = seq;
+    j.arrival_ns = arrival_ns;
+    j.flags = flags;
+    j.host_buf = hb;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->pending.push_back(j);
+    }
+    s->cv_sched.notify_one();
+    dd::clear_error();
+    return DEDISP_OK;
+}
+
+extern "C" dedisp_status dedisp_serve_poll(dedisp_server s, dedisp_chunk_result* out, int32_t cap,
+                                           int32_t* n_out, int32_t timeout_ms) {
+    if (!s || !n_out || (cap > 0 && !out)) return fail(DEDISP_ERR_INVALID_ARG, "bad poll arguments");
+    *n_out = 0;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (timeout_ms > 0 && s->results.empty() && s->async_error == DEDISP_OK)
+        s->cv_poll.wait_for(lk, std::chrono::milliseconds(timeout_ms),
+                            [&] { return !s->results.empty() || s->async_error != DEDISP_OK; });
+    if (s->async_error != DEDISP_OK) return fail(s->async_error, "%s", s->async_msg.c_str());
+    s->last_polled.clear();
+    while (!s->results.empty() && static_cast<int32_t>(s->last_polled.size()) < cap) {
+        s->last_polled.push_back(std::move(s->results.front()));
+        s->results.pop_front();
+    }
+    for (size_t i = 0; i < s->last_polled.size(); ++i) {
+        Result& r = s->last_polled[i];
+        r.r.events = r.events.empty() ? nullptr : r.events.data();
+        r.r.scores = r.scores.empty() ? nullptr : r.scores.data();
+        out[i] = r.r;
+    }
+    *n_out = static_cast<int32_t>(s->last_polled.size());
+    return DEDISP_OK;
+}
+
+extern "C" dedisp_status dedisp_serve_stats(dedisp_server s, dedisp_serve_stats_t* st) {
+    if (!s || !st) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> g(s->mu);
+    std::vector<int64_t> l = s->latencies;
+    std::sort(l.begin(), l.end());
+    auto pct = [&](double q) { return dedisp_percentile_ns(l.data(), static_cast<int64_t>(l.size()), q); };
+    st->chunks_done = static_cast<int64_t>(l.size());
+    st->p50_ns = pct(0.50);
+    st->p99_ns = pct(0.99);
+    st->max_ns = l.empty() ? 0 : l.back();
+    st->deadline_misses = s->misses;
+    st->batches = s->batches;
+    st->max_batch = s->max_batch;
+    st->mean_batch = s->batches ? static_cast<double>(s->batched_chunks) / s->batches : 0.0;
+    st->slots = static_cast<int32_t>(s->slots.size());
+    st->deadline_ns = static_cast<int64_t>(s->deadline_ns);
+    return DEDISP_OK;
+}
+
+extern "C" dedisp_status dedisp_serve_destroy(dedisp_server s) {
+    if (!s) return fail(DEDISP_ERR_INVALID_ARG, "server is NULL");
+    {
+        // let queued work finish before stopping
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv_poll.wait_for(lk, std::chrono::seconds(600), [&] {
+            return s->async_error != DEDISP_OK || (s->pending.empty() && s->inflight.empty() && s->ring_used == 0);
+        });
+        s->stop = true;
+    }
+    s->cv_sched.notify_all();
+    s->cv_done.notify_all();
+    if (s->sched.joinable()) s->sched.join();
+    if (s->compl_.joinable()) s->compl_.join();
+    (void)hipDeviceSynchronize();
+    free_server(s);
+    return DEDISP_OK;
+}

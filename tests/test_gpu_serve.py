@@ -1,0 +1,152 @@
+"""GPU tests of the streaming server: streamed results equal the oracle on
+each chunk's window (which itself equals the one-shot result restricted to
+that window), each chunk's result is the same alone and in the 13-beam mix,
+gaps, ordering errors and HBM-budget back-pressure."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import events_equal, log, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+WIDTHS = [1, 2, 4, 8, 16]
+K = 5.0
+C = 8192
+NCH = 256
+
+
+def _stream(seed, nchunks, dm_max):
+    """One beam of nchunks*C samples (generator: survey recipe at 256 ch)."""
+    fb = synth.make_beam(seed, nchunks * C, dm_max, 4, nchans=NCH, df=-400.0 / NCH, ndm=64,
+                         widths=WIDTHS, snr_thresh=K, name=f"s{seed}")
+    return fb
+
+
+def _chunk(fb, k):
+    bpc = fb.nchans // 4
+    return fb.packed[k * C * bpc:(k + 1) * C * bpc]
+
+
+def _drain(srv, want, timeout_s=120):
+    from paper_1112_0065_amd import _lib as L
+    got = []
+    t0 = time.time()
+    while len(got) < want and time.time() - t0 < timeout_s:
+        got += L.dedisp_serve_poll(srv, 64, 200)
+    assert len(got) == want, (len(got), want)
+    return got
+
+
+def _oracle_window(fb, dly, t_abs0, nsamps):
+    x = oracle.unpack_2bit(fb.packed, fb.nsamps, fb.nchans)[:, t_abs0:t_abs0 + nsamps]
+    out = oracle.dedisperse(x, dly)
+    return out, oracle.find_events(oracle.boxcar(out, WIDTHS), K)
+
+
+def test_stream_matches_oracle_windows():
+    from paper_1112_0065_amd import _lib as L
+    torch_dev()
+    nch = 4
+    fbs = [_stream(700 + b, nch, 80.0 + 30 * b) for b in range(3)]
+    plans = [L.dedisp_plan_create(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list) for fb in fbs]
+    budget = 40 * L.dedisp_serve_slot_bytes(plans, C, WIDTHS)
+    srv = L.dedisp_serve_create(plans, C, WIDTHS, K, budget)
+    for k in range(nch):
+        for b, fb in enumerate(fbs):
+            while not L.dedisp_serve_submit(srv, b, k, _chunk(fb, k), L.dedisp_now_ns()):
+                time.sleep(0.01)
+    res = _drain(srv, 3 * nch)
+    st = L.dedisp_serve_stats(srv)
+    log("serve stats", st)
+    assert st["chunks_done"] == 3 * nch and st["p50_ns"] <= st["p99_ns"] <= st["max_ns"]
+    for b, fb in enumerate(fbs):
+        dly = oracle.delay_table(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list)
+        md = int(dly.max())
+        H = md + WIDTHS[-1] - 1
+        one_shot = oracle.dedisperse(oracle.unpack_2bit(fb.packed, fb.nsamps, fb.nchans), dly)
+        mine = sorted([r for r in res if r["beam"] == b], key=lambda r: r["seq"])
+        assert [r["seq"] for r in mine] == list(range(nch))
+        covered = 0
+        for r in mine:
+            k = r["seq"]
+            start = 0 if k == 0 else k * C - H
+            nsamps = C if k == 0 else C + H
+            assert r["t_abs0"] == start and r["flags"] & L.CHUNK_GAP == 0
+            assert r["n_bx"] == (C - H if k == 0 else C)
+            out_w, ev_w = _oracle_window(fb, dly, start, nsamps)
+            # the window's series is the one-shot series over the same samples
+            assert (out_w == one_shot[:, start:start + out_w.shape[1]]).all()
+            events_equal(r["events"], ev_w)
+            covered += r["n_bx"]
+        # positions covered by the chunks are contiguous and complete
+        assert covered == nch * C - H
+
+
+def test_alone_equals_in_mix():
+    """A beam's chunk gives identical events alone and among 13 beams."""
+    from paper_1112_0065_amd import _lib as L
+    torch_dev()
+    fbs = [_stream(800 + b, 2, 60.0 + 10 * b) for b in range(13)]
+    plans = [L.dedisp_plan_create(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list) for fb in fbs]
+    budget = 30 * L.dedisp_serve_slot_bytes(plans, C, WIDTHS)
+    mix = L.dedisp_serve_create(plans, C, WIDTHS, K, budget)
+    for k in range(2):
+        for b in range(13):
+            while not L.dedisp_serve_submit(mix, b, k, _chunk(fbs[b], k), L.dedisp_now_ns()):
+                time.sleep(0.01)
+    res_mix = _drain(mix, 26)
+    st = L.dedisp_serve_stats(mix)
+    log("mix stats", st)
+    mix.close()
+    for b in (0, 6, 12):
+        alone = L.dedisp_serve_create([plans[b]], C, WIDTHS, K, budget)
+        for k in range(2):
+            assert L.dedisp_serve_submit(alone, 0, k, _chunk(fbs[b], k), L.dedisp_now_ns())
+        res_alone = _drain(alone, 2)
+        alone.close()
+        for k in range(2):
+            a = [r for r in res_alone if r["seq"] == k][0]
+            m = [r for r in res_mix if r["beam"] == b and r["seq"] == k][0]
+            assert a["t_abs0"] == m["t_abs0"] and a["n_events"] == m["n_events"]
+            assert a["events"].tobytes() == m["events"].tobytes()
+
+
+def test_gap_order_budget_and_backpressure():
+    from paper_1112_0065_amd import _lib as L
+    torch_dev()
+    fb = _stream(900, 6, 100.0)
+    plan = L.dedisp_plan_create(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list)
+    slot = L.dedisp_serve_slot_bytes([plan], C, WIDTHS)
+    with pytest.raises(L.DedispError) as e:
+        L.dedisp_serve_create([plan], C, WIDTHS, K, slot // 2)
+    assert e.value.status == L.ERR_OUT_OF_MEMORY
+    # one slot only: chunks queue behind each other; staging holds 2*slots+beams
+    srv = L.dedisp_serve_create([plan], C, WIDTHS, K, slot + (1 << 22))
+    assert L.dedisp_serve_stats(srv)["slots"] == 1
+    admitted = 0
+    busy = 0
+    for k in (0, 1, 3, 4, 5):           # chunk 2 never arrives: a gap
+        while not L.dedisp_serve_submit(srv, 0, k, _chunk(fb, k), L.dedisp_now_ns()):
+            busy += 1
+            time.sleep(0.005)
+        admitted += 1
+    with pytest.raises(L.DedispError) as e:
+        L.dedisp_serve_submit(srv, 0, 4, _chunk(fb, 4), L.dedisp_now_ns())
+    assert e.value.status == L.ERR_INVALID_ARG
+    res = sorted(_drain(srv, admitted), key=lambda r: r["seq"])
+    flags = {r["seq"]: r["flags"] for r in res}
+    assert flags[3] & L.CHUNK_GAP and not flags[1] & L.CHUNK_GAP and not flags[4] & L.CHUNK_GAP
+    r3 = [r for r in res if r["seq"] == 3][0]
+    dly = oracle.delay_table(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list)
+    H = int(dly.max()) + WIDTHS[-1] - 1
+    assert r3["t_abs0"] == 3 * C and r3["n_bx"] == C - H
+    _, ev = _oracle_window(fb, dly, 3 * C, C)
+    events_equal(r3["events"], ev)
+    st = L.dedisp_serve_stats(srv)
+    assert st["max_batch"] == 1 and st["chunks_done"] == admitted
+    log("one-slot stats", st, "busy retries", busy)
+    srv.close()
