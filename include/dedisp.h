@@ -59,6 +59,7 @@ typedef struct {
 } dedisp_event;
 
 typedef struct dedisp_plan_s* dedisp_plan;
+typedef struct triage_model_s* triage_model;
 
 /* ------------------------------------------------------------------------
  * Plan: the DM delay table (section 2.2).
@@ -288,7 +289,6 @@ dedisp_status dedisp_autotune(dedisp_plan plan, int64_t nsamps, dedisp_out_type 
  * arrays stay valid until the next poll.  destroy() drains queued work.
  * ------------------------------------------------------------------------ */
 typedef struct dedisp_server_s* dedisp_server;
-typedef struct triage_model_s* triage_model;
 
 enum {
     DEDISP_CHUNK_GAP = 1,       /* the chunk does not follow the previous one */
@@ -339,6 +339,51 @@ int64_t dedisp_now_ns(void);
  * (0 when not even one fits; at most 4096). */
 int64_t dedisp_percentile_ns(const int64_t* sorted, int64_t n, double q);
 int32_t dedisp_serve_admission(size_t budget, size_t resident, size_t slot_bytes);
+
+/* ------------------------------------------------------------------------
+ * Learned triage (section 2.1: interference can swamp detection with false
+ * positives; a small network scores candidates so that the plain S/N
+ * detector's events can be filtered).  Candidate tile of an event: 64 DM
+ * rows [d_peak-32, d_peak+32) shifted into [0, ndm), 256 columns at stride w
+ * (the event's width) from t0 = t_peak - 128 w clamped to
+ * [0, n_bx - 255 w - 1], value (n B - S1)/sqrt(D) of that row's series, 0
+ * outside the series or where D = 0, rounded to bfloat16.  Network: 4 x
+ * [3x3 conv pad 1 + bias, ReLU, 2x2 max-pool] with 1->32->32->32->32
+ * channels, global average, linear 32->1, logit; bfloat16 weights and
+ * activations, float32 accumulation; binary cross-entropy with logits,
+ * Adam (beta 0.9/0.999, eps 1e-8) on float32 master weights.  Reductions of
+ * gradients are in a fixed order: a training run is reproducible.
+ *
+ * triage_create: weights_path NULL -> He-normal initial weights from seed;
+ *   else a file written by triage_save (INVALID_ARG if missing, of another
+ *   version or holding non-finite weights: callers fall back to the plain
+ *   detector).
+ * tiles_bf16: device [n][64][256] bfloat16 bit patterns.  labels: device
+ *   float [n] in {0, 1}.  logits / scores (sigmoid): device float [n], may be
+ *   NULL.  loss: host, may be NULL (then no synchronisation).
+ * triage_tiles: tiles of n_events device events from a dedispersed uint16
+ *   series block and the workspace of the find_peaks call that found them.
+ * triage_set_params / triage_get_params: host float32 arrays of
+ *   triage_num_params() values in the order w1[32][1][3][3], b1, w2, b2,
+ *   w3, b3, w4, b4 ([32][32][3][3] and [32]), wf[32], bf[1]; grads (may be
+ *   NULL) receives the gradient of the last backward pass.
+ * ------------------------------------------------------------------------ */
+dedisp_status triage_create(const char* weights_path, uint64_t seed, triage_model* out);
+dedisp_status triage_destroy(triage_model m);
+int32_t triage_num_params(void);
+dedisp_status triage_set_params(triage_model m, const float* host_params, int32_t n);
+dedisp_status triage_get_params(triage_model m, float* host_params, float* host_grads, int32_t n);
+dedisp_status triage_tiles(const void* series_u16, int32_t ndm, int64_t nout, const int32_t* widths,
+                           int32_t nwidths, const void* peaks_workspace, const dedisp_event* events,
+                           int32_t n_events, uint16_t* tiles_out, dedisp_stream stream);
+dedisp_status triage_forward(triage_model m, const uint16_t* tiles_bf16, int32_t n, float* logits,
+                             float* scores, dedisp_stream stream);
+dedisp_status triage_forward_backward(triage_model m, const uint16_t* tiles_bf16,
+                                      const float* labels, int32_t n, float* loss,
+                                      dedisp_stream stream);
+dedisp_status triage_train_step(triage_model m, const uint16_t* tiles_bf16, const float* labels,
+                                int32_t n, float lr, float* loss, dedisp_stream stream);
+dedisp_status triage_save(triage_model m, const char* path);
 
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* dedisp_last_error(void);

@@ -8,7 +8,10 @@ Python binding (``_lib``) plus small device-memory helpers (``api``).
 """
 from ._lib import (  # noqa: F401
     Batch, DedispError, dedisp_autotune, dedisp_batch_create, dedisp_batch_execute,
-    dedisp_batch_info, EVENT_DTYPE, OUT_I32, OUT_U16, Plan, boxcar_filter, dedisp_default_tile,
+    dedisp_batch_info, Model, Server, triage_create, triage_forward, triage_forward_backward,
+    triage_get_params, triage_num_params, triage_save, triage_set_params, triage_tiles,
+    triage_train_step, dedisp_serve_create, dedisp_serve_submit, dedisp_serve_poll,
+    dedisp_serve_stats, dedisp_now_ns, EVENT_DTYPE, OUT_I32, OUT_U16, Plan, boxcar_filter, dedisp_default_tile,
     dedisp_execute, dedisp_execute_repacked, dedisp_execute_tile, dedisp_repack, dedisp_last_error, dedisp_plan_copy_delays,
     dedisp_plan_create, dedisp_plan_info, dedisp_tile_candidates, dedisp_workspace_bytes,
     events_from_buffer, find_peaks, find_peaks_read_stats, find_peaks_workspace_bytes, lib,

@@ -105,6 +105,16 @@ def lib() -> C.CDLL:
         "dedisp_now_ns": (i64, []),
         "dedisp_percentile_ns": (i64, [P(i64), i64, f64]),
         "dedisp_serve_admission": (i32, [sz, sz, sz]),
+        "triage_create": (i32, [C.c_char_p, C.c_uint64, P(vp)]),
+        "triage_destroy": (i32, [vp]),
+        "triage_num_params": (i32, []),
+        "triage_set_params": (i32, [vp, P(f32), i32]),
+        "triage_get_params": (i32, [vp, P(f32), P(f32), i32]),
+        "triage_tiles": (i32, [vp, i32, i64, P(i32), i32, vp, vp, i32, vp, vp]),
+        "triage_forward": (i32, [vp, vp, i32, vp, vp, vp]),
+        "triage_forward_backward": (i32, [vp, vp, vp, i32, P(f32), vp]),
+        "triage_train_step": (i32, [vp, vp, vp, i32, f32, P(f32), vp]),
+        "triage_save": (i32, [vp, C.c_char_p]),
         "dedisp_last_error": (C.c_char_p, []),
         "dedisp_version": (C.c_char_p, []),
     }
@@ -468,3 +478,72 @@ def dedisp_percentile_ns(values, q: float) -> int:
 
 def dedisp_serve_admission(budget: int, resident: int, slot_bytes: int) -> int:
     return int(lib().dedisp_serve_admission(int(budget), int(resident), int(slot_bytes)))
+
+
+# ---------------------------------------------------------------------------
+# Triage network
+# ---------------------------------------------------------------------------
+
+class Model:
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.triage_destroy(self.handle)
+            self.handle = None
+
+
+def triage_create(weights_path: Optional[str] = None, seed: int = 0) -> Model:
+    h = C.c_void_p()
+    _check(lib().triage_create(weights_path.encode() if weights_path else None, int(seed),
+                               C.byref(h)))
+    return Model(h.value)
+
+
+def triage_num_params() -> int:
+    return int(lib().triage_num_params())
+
+
+def triage_set_params(m: Model, params: np.ndarray):
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _check(lib().triage_set_params(m.handle, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+
+
+def triage_get_params(m: Model):
+    n = triage_num_params()
+    p = np.empty(n, np.float32)
+    g = np.empty(n, np.float32)
+    _check(lib().triage_get_params(m.handle, p.ctypes.data_as(C.POINTER(C.c_float)),
+                                   g.ctypes.data_as(C.POINTER(C.c_float)), n))
+    return p, g
+
+
+def triage_tiles(series, ndm: int, nout: int, widths, peaks_ws, events_dev, n_events: int,
+                 tiles_out, stream=None):
+    _check(lib().triage_tiles(_ptr(series), int(ndm), int(nout), _i32arr(widths), len(widths),
+                              _ptr(peaks_ws), _ptr(events_dev), int(n_events), _ptr(tiles_out),
+                              _stream(stream)))
+
+
+def triage_forward(m: Model, tiles, n: int, logits=None, scores=None, stream=None):
+    _check(lib().triage_forward(m.handle, _ptr(tiles), int(n), _ptr(logits), _ptr(scores),
+                                _stream(stream)))
+
+
+def triage_forward_backward(m: Model, tiles, labels, n: int, stream=None) -> float:
+    loss = C.c_float()
+    _check(lib().triage_forward_backward(m.handle, _ptr(tiles), _ptr(labels), int(n),
+                                         C.byref(loss), _stream(stream)))
+    return float(loss.value)
+
+
+def triage_train_step(m: Model, tiles, labels, n: int, lr: float = 1e-3, stream=None) -> float:
+    loss = C.c_float()
+    _check(lib().triage_train_step(m.handle, _ptr(tiles), _ptr(labels), int(n), float(lr),
+                                   C.byref(loss), _stream(stream)))
+    return float(loss.value)
+
+
+def triage_save(m: Model, path: str):
+    _check(lib().triage_save(m.handle, path.encode()))

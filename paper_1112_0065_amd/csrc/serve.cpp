@@ -275,8 +275,9 @@ void completer(dedisp_server_s* s) {
             if (e == hipSuccess && s->model) {
                 const dedisp_plan_s* p = s->plans[j.beam];
                 const int64_t nout = j.nsamps - p->max_delay;
-                dedisp_status tst = dd::triage_score_events(s->model, s->slots[j.slot].out, p->ndm, nout,
-                                                            s->W, r.events.data(), m, &r.scores,
+                dedisp_status tst = dd::triage_score_events(s->model, s->slots[j.slot].out,
+                                                            s->slots[j.slot].pk_ws, p->ndm, nout, s->W,
+                                                            s->slots[j.slot].d_events, m, &r.scores,
                                                             s->done_s);
                 if (tst != DEDISP_OK) flags |= DEDISP_CHUNK_FALLBACK;
             } else if (!s->model) {

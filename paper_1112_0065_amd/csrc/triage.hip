@@ -1,0 +1,559 @@
+// Triage network kernels: candidate tiles, a 4-layer bfloat16 CNN forward and
+// backward pass, and Adam.
+//
+// The paper's section 2.1 names radio-frequency interference as the main
+// source of false events.  This network scores (DM, time) candidate tiles so
+// that interference can be rejected; the plain S/N detector remains the
+// fallback.  Layout: activations NHWC bfloat16 (channels innermost, 64 bytes
+// per pixel), float32 accumulation.  The 32->32 convolutions (forward and
+// input gradient) are implicit GEMMs on the bf16 matrix cores
+// (v_mfma_f32_16x16x16_bf16: M = pixels, N = 32 output channels,
+// K = 9 taps x 32 input channels = 288); the weight gradient is a GEMM over
+// pixels (M = 32, N = 32 per tap, K = pixels) on the same instruction,
+// reduced across blocks in a fixed order (no float atomics: training is
+// reproducible bit for bit).  The 1->32 first layer (K = 9) runs on VALU.
+#include <cstdint>
+
+#include "triage_kernels.hpp"
+
+namespace tk {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even (finite inputs)
+    return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
+
+__device__ __forceinline__ bf16x4 load4(const uint16_t* p) {
+    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    bf16x4 r;
+    r[0] = static_cast<short>(v.x & 0xFFFF);
+    r[1] = static_cast<short>(v.x >> 16);
+    r[2] = static_cast<short>(v.y & 0xFFFF);
+    r[3] = static_cast<short>(v.y >> 16);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Candidate tiles: one block of 256 threads (one per column) per (event, row).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void tiles_kernel(const uint16_t* __restrict__ series, int ndm,
+                                                    int64_t nout, int64_t nbx, TileWidths W,
+                                                    const dedisp_event* __restrict__ events,
+                                                    const uint64_t* __restrict__ s1,
+                                                    const double* __restrict__ sqrt_d,
+                                                    uint16_t* __restrict__ tiles) {
+    const int e = blockIdx.x;
+    const int r = blockIdx.y;
+    const int j = threadIdx.x;
+    const dedisp_event ev = events[e];
+    const int w = W.w[ev.width_idx];
+    int d0 = ev.dm_idx - 32;
+    d0 = min(max(d0, 0), max(ndm - 64, 0));
+    int64_t t0 = ev.t_peak - 128 * static_cast<int64_t>(w);
+    t0 = min(max(t0, int64_t(0)), max(nbx - 255 * static_cast<int64_t>(w) - 1, int64_t(0)));
+    const int d = d0 + r;
+    float v = 0.0f;
+    const int64_t t = t0 + static_cast<int64_t>(j) * w;
+    if (d < ndm && t < nbx) {
+        const int sidx = ev.width_idx * ndm + d;
+        const double sq = sqrt_d[sidx];
+        if (sq > 0.0) {
+            const uint16_t* row = series + static_cast<int64_t>(d) * nout + t;
+            uint32_t b = 0;
+            for (int k = 0; k < w; ++k) b += row[k];
+            const int64_t lval = nbx * static_cast<int64_t>(b) - static_cast<int64_t>(s1[sidx]);
+            v = static_cast<float>(static_cast<double>(lval) / sq);
+        }
+    }
+    tiles[(static_cast<int64_t>(e) * 64 + r) * 256 + j] = f2bf(v);
+}
+
+// ---------------------------------------------------------------------------
+// Layer 1: 1 -> 32 channels, 3x3, pad 1, + bias, ReLU; VALU.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void conv1_fwd_kernel(const uint16_t* __restrict__ x, int N,
+                                                        const uint16_t* __restrict__ w1b,
+                                                        const float* __restrict__ b1,
+                                                        uint16_t* __restrict__ a) {
+    __shared__ float ws[kCH * 9];
+    __shared__ float bs[kCH];
+    for (int i = threadIdx.x; i < kCH * 9; i += blockDim.x) ws[i] = bf2f(w1b[i]);
+    if (threadIdx.x < kCH) bs[threadIdx.x] = b1[threadIdx.x];
+    __syncthreads();
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t npix = static_cast<int64_t>(N) * 64 * 256;
+    if (p >= npix) return;
+    const int xx = static_cast<int>(p % 256);
+    const int yy = static_cast<int>((p / 256) % 64);
+    const int64_t n = p / (64 * 256);
+    float in[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int y2 = yy + t / 3 - 1, x2 = xx + t % 3 - 1;
+        in[t] = (y2 >= 0 && y2 < 64 && x2 >= 0 && x2 < 256) ? bf2f(x[(n * 64 + y2) * 256 + x2]) : 0.0f;
+    }
+    uint32_t packed[kCH / 2];
+#pragma unroll
+    for (int c = 0; c < kCH; c += 2) {
+        float z0 = bs[c], z1 = bs[c + 1];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            z0 += ws[c * 9 + t] * in[t];
+            z1 += ws[(c + 1) * 9 + t] * in[t];
+        }
+        packed[c / 2] = static_cast<uint32_t>(f2bf(fmaxf(z0, 0.0f))) |
+                        (static_cast<uint32_t>(f2bf(fmaxf(z1, 0.0f))) << 16);
+    }
+    uint4* dst = reinterpret_cast<uint4*>(a + p * kCH);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        dst[q] = make_uint4(packed[4 * q], packed[4 * q + 1], packed[4 * q + 2], packed[4 * q + 3]);
+}
+
+// ---------------------------------------------------------------------------
+// 32 -> 32 convolution as an implicit GEMM on MFMA.  One wave = 32 pixels of
+// one image row x 32 output channels (2 x 2 tiles of 16 x 16), K = 288 in 18
+// steps of 16 (one tap, half of the input channels, per step).
+// MODE 0: out = bf16(ReLU(acc + bias)); MODE 1: out = acc (float32).
+// wt: [co][tap][ci] bf16 (forward) or the flipped, transposed kernel for the
+// input gradient.
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(64) void conv32_mfma_kernel(const uint16_t* __restrict__ x, int N, int H,
+                                                         int W, const uint16_t* __restrict__ wt,
+                                                         const float* __restrict__ bias,
+                                                         void* __restrict__ out) {
+    const int lane = threadIdx.x;
+    const int segs = W / 32;
+    const int64_t blk = blockIdx.x;
+    const int xs = static_cast<int>(blk % segs) * 32;
+    const int y = static_cast<int>((blk / segs) % H);
+    const int64_t n = blk / (static_cast<int64_t>(segs) * H);
+    const int row = lane & 15;       // A row (pixel) / B column (channel) within a tile
+    const int kq = lane >> 4;        // which 4-element K slice
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x4 zero4 = bf16x4{0, 0, 0, 0};
+#pragma unroll 2
+    for (int s = 0; s < 18; ++s) {
+        const int tap = s >> 1;
+        const int ci0 = 16 * (s & 1) + 4 * kq;
+        const int y2 = y + tap / 3 - 1;
+        bf16x4 afr[2], bfr[2];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            const int x2 = xs + 16 * rt + row + tap % 3 - 1;
+            const bool ok = y2 >= 0 && y2 < H && x2 >= 0 && x2 < W;
+            afr[rt] = ok ? load4(x + ((n * H + y2) * W + x2) * kCH + ci0) : zero4;
+        }
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) bfr[ct] = load4(wt + ((16 * ct + row) * 9 + tap) * kCH + ci0);
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(afr[rt], bfr[ct], acc[rt][ct], 0, 0, 0);
+    }
+    // D[i][c]: lane holds rows 4*kq + j (pixels), column row (channel)
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int xo = xs + 16 * rt + 4 * kq + j;
+                const int co = 16 * ct + row;
+                const int64_t o = ((n * H + y) * W + xo) * kCH + co;
+                if (MODE == 0)
+                    static_cast<uint16_t*>(out)[o] = f2bf(fmaxf(acc[rt][ct][j] + bias[co], 0.0f));
+                else
+                    static_cast<float*>(out)[o] = acc[rt][ct][j];
+            }
+}
+
+// ---------------------------------------------------------------------------
+// 2x2 max-pool (first maximum in raster order) with the winner's index.
+// ---------------------------------------------------------------------------
+__global__ void maxpool_fwd_kernel(const uint16_t* __restrict__ a, int N, int H, int W,
+                                   uint16_t* __restrict__ p, uint8_t* __restrict__ idx) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int H2 = H / 2, W2 = W / 2;
+    const int64_t total = static_cast<int64_t>(N) * H2 * W2 * kCH;
+    if (i >= total) return;
+    const int c = static_cast<int>(i % kCH);
+    const int x2 = static_cast<int>((i / kCH) % W2);
+    const int y2 = static_cast<int>((i / (kCH * W2)) % H2);
+    const int64_t n = i / (static_cast<int64_t>(kCH) * W2 * H2);
+    float best = -1.0f;
+    int bi = 0;
+    uint16_t bv = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int y = 2 * y2 + (k >> 1), x = 2 * x2 + (k & 1);
+        const uint16_t v = a[((n * H + y) * W + x) * kCH + c];
+        const float f = bf2f(v);
+        if (k == 0 || f > best) {
+            best = f;
+            bi = k;
+            bv = v;
+        }
+    }
+    p[i] = bv;
+    idx[i] = static_cast<uint8_t>(bi);
+}
+
+// Global average over the 4x16 map, then the 32 -> 1 linear layer.
+__global__ void gap_fc_fwd_kernel(const uint16_t* __restrict__ p4, int N, const float* __restrict__ wf,
+                                  const float* __restrict__ bf, float* __restrict__ g,
+                                  float* __restrict__ logits) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float lg = bf[0];
+    for (int c = 0; c < kCH; ++c) {
+        float s = 0.0f;
+        for (int q = 0; q < 64; ++q) s += bf2f(p4[(static_cast<int64_t>(n) * 64 + q) * kCH + c]);
+        s *= (1.0f / 64.0f);
+        g[n * kCH + c] = s;
+        lg += s * wf[c];
+    }
+    logits[n] = lg;
+}
+
+// Loss (mean binary cross-entropy with logits) and d loss / d logit; one block.
+__global__ __launch_bounds__(256) void bce_kernel(const float* __restrict__ logits,
+                                                  const float* __restrict__ labels, int N,
+                                                  float* __restrict__ dlogit, float* __restrict__ loss) {
+    __shared__ float part[256];
+    float s = 0.0f;
+    for (int n = threadIdx.x; n < N; n += 256) {
+        const float z = logits[n], y = labels[n];
+        s += fmaxf(z, 0.0f) - z * y + log1pf(expf(-fabsf(z)));
+        dlogit[n] = (1.0f / (1.0f + expf(-z)) - y) / static_cast<float>(N);
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (static_cast<int>(threadIdx.x) < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = part[0] / static_cast<float>(N);
+}
+
+// Linear + average backward: gradients of wf, bf; d p4 (float32).
+__global__ void fc_bwd_kernel(const float* __restrict__ dlogit, const float* __restrict__ g, int N,
+                              const float* __restrict__ wf, float* __restrict__ gwf,
+                              float* __restrict__ gbf) {
+    const int c = threadIdx.x;
+    if (c < kCH) {
+        float s = 0.0f;
+        for (int n = 0; n < N; ++n) s += dlogit[n] * g[n * kCH + c];
+        gwf[c] = s;
+    } else if (c == kCH) {
+        float s = 0.0f;
+        for (int n = 0; n < N; ++n) s += dlogit[n];
+        gbf[0] = s;
+    }
+}
+
+__global__ void gap_bwd_kernel(const float* __restrict__ dlogit, const float* __restrict__ wf, int N,
+                               float* __restrict__ dp4) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= static_cast<int64_t>(N) * 64 * kCH) return;
+    const int c = static_cast<int>(i % kCH);
+    const int64_t n = i / (64 * kCH);
+    dp4[i] = dlogit[n] * wf[c] * (1.0f / 64.0f);
+}
+
+// Max-pool backward + ReLU mask, rounded to bf16: dz = bf16(dA * (a > 0)).
+__global__ void pool_relu_bwd_kernel(const float* __restrict__ dp, const uint8_t* __restrict__ idx,
+                                     const uint16_t* __restrict__ a, int N, int H, int W,
+                                     uint16_t* __restrict__ dz) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t total = static_cast<int64_t>(N) * H * W * kCH;
+    if (i >= total) return;
+    const int c = static_cast<int>(i % kCH);
+    const int x = static_cast<int>((i / kCH) % W);
+    const int y = static_cast<int>((i / (kCH * W)) % H);
+    const int64_t n = i / (static_cast<int64_t>(kCH) * W * H);
+    const int64_t pi = ((n * (H / 2) + y / 2) * (W / 2) + x / 2) * kCH + c;
+    const int k = ((y & 1) << 1) | (x & 1);
+    float v = (idx[pi] == k) ? dp[pi] : 0.0f;
+    if (!(bf2f(a[i]) > 0.0f)) v = 0.0f;
+    dz[i] = f2bf(v);
+}
+
+// Weight gradient of a 32 -> 32 layer for one tap, over `rows` consecutive
+// image rows per block: dW_tap[co][ci] = sum_pixels dz[p][co] x[p + tap][ci].
+// MFMA with M = co, N = ci, K = pixels (16 per step).  Writes one partial per
+// block: part[blk][tap][co][ci].
+__global__ __launch_bounds__(64) void wgrad32_mfma_kernel(const uint16_t* __restrict__ x,
+                                                          const uint16_t* __restrict__ dz, int N,
+                                                          int H, int W, int rows,
+                                                          float* __restrict__ part) {
+    const int lane = threadIdx.x;
+    const int tap = blockIdx.y;
+    const int ky = tap / 3 - 1, kx = tap % 3 - 1;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rows;
+    const int64_t nrows = static_cast<int64_t>(N) * H;
+    const int idx16 = lane & 15;
+    const int kq = lane >> 4;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t rr = r0; rr < min(r0 + rows, nrows); ++rr) {
+        const int y = static_cast<int>(rr % H);
+        const int64_t n = rr / H;
+        const int y2 = y + ky;
+        const bool yok = y2 >= 0 && y2 < H;
+        for (int x0 = 0; x0 < W; x0 += 16) {
+            bf16x4 afr[2], bfr[2];
+            // A[co][k = pixel]: 4 consecutive pixels of one output channel
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) {
+                const int co = 16 * rt + idx16;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int xp = x0 + 4 * kq + j;
+                    afr[rt][j] = static_cast<short>(dz[((n * H + y) * W + xp) * kCH + co]);
+                }
+            }
+            // B[k = pixel][ci]: shifted input
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) {
+                const int ci = 16 * ct + idx16;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int x2 = x0 + 4 * kq + j + kx;
+                    const bool ok = yok && x2 >= 0 && x2 < W;
+                    bfr[ct][j] = ok ? static_cast<short>(x[((n * H + y2) * W + x2) * kCH + ci]) : short(0);
+                }
+            }
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct)
+                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(afr[rt], bfr[ct], acc[rt][ct], 0, 0, 0);
+        }
+    }
+    float* dst = part + (static_cast<int64_t>(blockIdx.x) * 9 + tap) * kCH * kCH;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                dst[(16 * rt + 4 * kq + j) * kCH + 16 * ct + idx16] = acc[rt][ct][j];
+}
+
+// Layer-1 weight gradient (Cin = 1) and every layer's bias gradient partials:
+// block = `rows` image rows; part[blk][k] over k < 288 (+32 bias) for layer 1,
+// or part[blk][co] (bias only) otherwise.
+__global__ __launch_bounds__(320) void wgrad1_bias_kernel(const uint16_t* __restrict__ x,
+                                                          const uint16_t* __restrict__ dz, int N, int H,
+                                                          int W, int rows, int with_w,
+                                                          float* __restrict__ part, int stride) {
+    const int k = threadIdx.x;   // < 288: weight (co = k / 9, tap = k % 9); 288..319: bias of co = k - 288
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rows;
+    const int64_t nrows = static_cast<int64_t>(N) * H;
+    float s = 0.0f;
+    if (k < 288 && with_w) {
+        const int co = k / 9, tap = k % 9;
+        const int ky = tap / 3 - 1, kx = tap % 3 - 1;
+        for (int64_t rr = r0; rr < min(r0 + rows, nrows); ++rr) {
+            const int y = static_cast<int>(rr % H);
+            const int64_t n = rr / H;
+            const int y2 = y + ky;
+            if (y2 < 0 || y2 >= H) continue;
+            for (int xx = 0; xx < W; ++xx) {
+                const int x2 = xx + kx;
+                if (x2 < 0 || x2 >= W) continue;
+                s += bf2f(dz[((n * H + y) * W + xx) * kCH + co]) * bf2f(x[(n * H + y2) * W + x2]);
+            }
+        }
+        part[static_cast<int64_t>(blockIdx.x) * stride + k] = s;
+    } else if (k >= 288) {
+        const int co = k - 288;
+        for (int64_t rr = r0; rr < min(r0 + rows, nrows); ++rr)
+            for (int xx = 0; xx < W; ++xx) s += bf2f(dz[(rr * W + xx) * kCH + co]);
+        part[static_cast<int64_t>(blockIdx.x) * stride + (with_w ? 288 : 0) + co] = s;
+    }
+}
+
+// out[i] = sum over blocks b (in order) of part[b * stride + i], i < n.
+__global__ void reduce_parts_kernel(const float* __restrict__ part, int nparts, int stride, int n,
+                                    float* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int b = 0; b < nparts; ++b) s += part[static_cast<int64_t>(b) * stride + i];
+    out[i] = s;
+}
+
+// dW (layout [tap][co][ci]) -> the master layout [co][ci][ky][kx].
+__global__ void wgrad_to_master_kernel(const float* __restrict__ d_tap, float* __restrict__ g) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kCH * kCH * 9) return;
+    const int tap = i % 9, ci = (i / 9) % kCH, co = i / (9 * kCH);
+    g[i] = d_tap[(tap * kCH + co) * kCH + ci];
+}
+
+// Adam on float32 master weights.
+__global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, int n, float lr, float b1, float b2, float eps,
+                            float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// bf16 copies of the convolution weights in the kernels' layouts.
+__global__ void derive_weights_kernel(const float* __restrict__ master, Offsets off,
+                                      uint16_t* __restrict__ w1b, uint16_t* __restrict__ wfwd,
+                                      uint16_t* __restrict__ wdg) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kCH * 9) w1b[i] = f2bf(master[off.w[0] + i]);   // [co][tap]
+    const int per = kCH * 9 * kCH;
+    if (i >= 3 * per) return;
+    const int l = i / per;          // layers 2..4 -> 0..2
+    const int r = i % per;          // master index within [co][ci][ky][kx]
+    const int tap = r % 9, ci = (r / 9) % kCH, co = r / (9 * kCH);
+    const uint16_t b = f2bf(master[off.w[l + 1] + r]);
+    wfwd[l * per + (co * 9 + tap) * kCH + ci] = b;            // [co][tap][ci]
+    wdg[l * per + (ci * 9 + (8 - tap)) * kCH + co] = b;       // [ci][flipped tap][co]
+}
+
+__global__ void sigmoid_kernel(const float* __restrict__ z, int n, float* __restrict__ s) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) s[i] = 1.0f / (1.0f + expf(-z[i]));
+}
+
+__global__ void finite_check_kernel(const float* __restrict__ a, int n, int* __restrict__ bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !isfinite(a[i])) atomicAdd(bad, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------
+
+static inline unsigned blocks(int64_t n, int t) { return static_cast<unsigned>((n + t - 1) / t); }
+
+hipError_t launch_tiles(const uint16_t* series, int ndm, int64_t nout, int64_t nbx, const TileWidths& W,
+                        const dedisp_event* events, int nev, const uint64_t* s1, const double* sqrt_d,
+                        uint16_t* tiles, hipStream_t s) {
+    if (nev <= 0) return hipSuccess;
+    hipLaunchKernelGGL(tiles_kernel, dim3(nev, 64), dim3(256), 0, s, series, ndm, nout, nbx, W, events,
+                       s1, sqrt_d, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_derive(const float* master, const Offsets& off, uint16_t* w1b, uint16_t* wfwd,
+                         uint16_t* wdg, hipStream_t s) {
+    hipLaunchKernelGGL(derive_weights_kernel, dim3(blocks(3 * kCH * 9 * kCH, 256)), dim3(256), 0, s, master,
+                       off, w1b, wfwd, wdg);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward(const Net& net, const uint16_t* tiles, int N, hipStream_t s) {
+    const int64_t pix1 = static_cast<int64_t>(N) * 64 * 256;
+    hipLaunchKernelGGL(conv1_fwd_kernel, dim3(blocks(pix1, 256)), dim3(256), 0, s, tiles, N, net.w1b,
+                       net.master + net.off.b[0], net.a[0]);
+    int H = 64, W = 256;
+    for (int l = 0; l < 4; ++l) {
+        if (l > 0) {
+            const int64_t nb = static_cast<int64_t>(N) * H * (W / 32);
+            hipLaunchKernelGGL(conv32_mfma_kernel<0>, dim3(static_cast<unsigned>(nb)), dim3(64), 0, s,
+                               net.p[l - 1], N, H, W, net.wfwd + (l - 1) * kCH * 9 * kCH,
+                               net.master + net.off.b[l], static_cast<void*>(net.a[l]));
+        }
+        const int64_t np = static_cast<int64_t>(N) * (H / 2) * (W / 2) * kCH;
+        hipLaunchKernelGGL(maxpool_fwd_kernel, dim3(blocks(np, 256)), dim3(256), 0, s, net.a[l], N, H, W,
+                           net.p[l], net.idx[l]);
+        H /= 2;
+        W /= 2;
+    }
+    hipLaunchKernelGGL(gap_fc_fwd_kernel, dim3(blocks(N, 64)), dim3(64), 0, s, net.p[3], N,
+                       net.master + net.off.wf, net.master + net.off.bf, net.g, net.logits);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward(const Net& net, const uint16_t* tiles, const float* labels, int N,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(bce_kernel, dim3(1), dim3(256), 0, s, net.logits, labels, N, net.dlogit, net.loss);
+    hipLaunchKernelGGL(fc_bwd_kernel, dim3(1), dim3(64), 0, s, net.dlogit, net.g, N, net.master + net.off.wf,
+                       net.grad + net.off.wf, net.grad + net.off.bf);
+    hipLaunchKernelGGL(gap_bwd_kernel, dim3(blocks(static_cast<int64_t>(N) * 64 * kCH, 256)), dim3(256), 0,
+                       s, net.dlogit, net.master + net.off.wf, N, net.dp);
+    const int Hs[4] = {64, 32, 16, 8}, Ws[4] = {256, 128, 64, 32};
+    for (int l = 3; l >= 0; --l) {
+        const int H = Hs[l], W = Ws[l];
+        const int64_t ne = static_cast<int64_t>(N) * H * W * kCH;
+        hipLaunchKernelGGL(pool_relu_bwd_kernel, dim3(blocks(ne, 256)), dim3(256), 0, s, net.dp, net.idx[l],
+                           net.a[l], N, H, W, net.dz);
+        const int64_t nrows = static_cast<int64_t>(N) * H;
+        const int rows = kRowsPerBlock;
+        const int nparts = static_cast<int>((nrows + rows - 1) / rows);
+        const uint16_t* xin = l == 0 ? tiles : net.p[l - 1];
+        if (l == 0) {
+            hipLaunchKernelGGL(wgrad1_bias_kernel, dim3(nparts), dim3(320), 0, s, xin, net.dz, N, H, W, rows, 1,
+                               net.part, 320);
+            hipLaunchKernelGGL(reduce_parts_kernel, dim3(blocks(288, 256)), dim3(256), 0, s, net.part, nparts,
+                               320, 288, net.grad + net.off.w[0]);
+            hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(64), 0, s, net.part + 288, nparts, 320, kCH,
+                               net.grad + net.off.b[0]);
+        } else {
+            hipLaunchKernelGGL(wgrad32_mfma_kernel, dim3(nparts, 9), dim3(64), 0, s, xin, net.dz, N, H, W, rows,
+                               net.part);
+            hipLaunchKernelGGL(reduce_parts_kernel, dim3(blocks(9 * kCH * kCH, 256)), dim3(256), 0, s, net.part,
+                               nparts, 9 * kCH * kCH, 9 * kCH * kCH, net.dtap);
+            hipLaunchKernelGGL(wgrad_to_master_kernel, dim3(blocks(9 * kCH * kCH, 256)), dim3(256), 0, s,
+                               net.dtap, net.grad + net.off.w[l]);
+            hipLaunchKernelGGL(wgrad1_bias_kernel, dim3(nparts), dim3(320), 0, s, xin, net.dz, N, H, W, rows, 0,
+                               net.part, kCH);
+            hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(64), 0, s, net.part, nparts, kCH, kCH,
+                               net.grad + net.off.b[l]);
+            // input gradient -> d p_{l-1} (float32)
+            const int64_t nb = static_cast<int64_t>(N) * H * (W / 32);
+            hipLaunchKernelGGL(conv32_mfma_kernel<1>, dim3(static_cast<unsigned>(nb)), dim3(64), 0, s, net.dz, N, H,
+                               W, net.wdg + (l - 1) * kCH * 9 * kCH, static_cast<const float*>(nullptr),
+                               static_cast<void*>(net.dp));
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(const Net& net, float lr, int step, hipStream_t s) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.0f - powf(b1, static_cast<float>(step));
+    const float c2 = 1.0f - powf(b2, static_cast<float>(step));
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks(kNumParams, 256)), dim3(256), 0, s, net.master, net.grad, net.m,
+                       net.v, kNumParams, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_sigmoid(const float* z, int n, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(sigmoid_kernel, dim3(blocks(n, 256)), dim3(256), 0, s, z, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_finite_check(const float* a, int n, int* bad, hipStream_t s) {
+    hipLaunchKernelGGL(finite_check_kernel, dim3(blocks(n, 256)), dim3(256), 0, s, a, n, bad);
+    return hipGetLastError();
+}
+
+}  // namespace tk
