@@ -179,11 +179,19 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* w
 // (values outside [0, nout) count as 0): pl[i] = sum_{k<i} s[first+k].
 template <typename T>
 __device__ void load_prefix(const T* __restrict__ row, int64_t nout, int64_t first, int n,
-                            uint32_t* pl, uint32_t* wave_tot) {
+                            uint32_t* pl, uint32_t* wave_tot, uint32_t* vmax = nullptr) {
     // coalesced load of the raw values into pl[1..n)
+    uint32_t m = 0;
     for (int i = threadIdx.x; i < n - 1; i += kThreads) {
         const int64_t t = first + i;
-        pl[i + 1] = (t >= 0 && t < nout) ? static_cast<uint32_t>(row[t]) : 0u;
+        const uint32_t v = (t >= 0 && t < nout) ? static_cast<uint32_t>(row[t]) : 0u;
+        pl[i + 1] = v;
+        m = max(m, v);
+    }
+    if (vmax) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) m = max(m, static_cast<uint32_t>(__shfl_xor(m, o, 64)));
+        if ((threadIdx.x & 63) == 0) atomicMax(vmax, m);
     }
     __syncthreads();
     // each thread scans a contiguous chunk (odd chunk stride: no bank conflicts)
@@ -234,7 +242,39 @@ __global__ __launch_bounds__(kThreads) void boxcar_kernel(const T* __restrict__ 
     }
 }
 
-// Pass 1: per (width, DM, segment) partial sums of B and B^2.
+// Pass 1: per (width, DM, segment) partial sums of B and B^2 and the largest B.
+// Per thread and width at most L/256 <= 32 positions are summed in registers.
+// When every B of the block's window is below 2^26 (the largest raw value
+// times w_max says so) a 64-bit square sum cannot overflow even after the
+// 64-lane reduction; otherwise the sums are carried as 128-bit values.
+template <bool SMALL>
+__device__ __forceinline__ void width_sums(const uint32_t* pl, int npos, int w, uint64_t* s1_out,
+                                           u128* s2_out, uint32_t* mx_out) {
+    uint64_t s1 = 0, lo = 0, hi = 0;
+    uint32_t mx = 0;
+    for (int i = threadIdx.x; i < npos; i += kThreads) {
+        const uint32_t b = pl[i + 1 + w] - pl[i + 1];
+        s1 += b;
+        const uint64_t sq = static_cast<uint64_t>(b) * b;   // one v_mad_u64_u32 when SMALL
+        lo += sq;
+        if (!SMALL) hi += lo < sq ? 1u : 0u;
+        mx = max(mx, b);
+    }
+    s1 = wave_sum_u64(s1);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mx = max(mx, static_cast<uint32_t>(__shfl_xor(mx, o, 64)));
+    if (SMALL) {
+        *s2_out = wave_sum_u64(lo);
+    } else {
+        const uint64_t a = wave_sum_u64(lo & 0xFFFFFFFFull);
+        const uint64_t b = wave_sum_u64(lo >> 32);
+        const uint64_t c = wave_sum_u64(hi);
+        *s2_out = static_cast<u128>(a) + (static_cast<u128>(b) << 32) + (static_cast<u128>(c) << 64);
+    }
+    *s1_out = s1;
+    *mx_out = mx;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void boxcar_stats_kernel(const T* __restrict__ in,
                                                                 int64_t nout, int64_t nbx,
@@ -242,35 +282,32 @@ __global__ __launch_bounds__(kThreads) void boxcar_stats_kernel(const T* __restr
                                                                 dd::PeaksWs ws) {
     extern __shared__ uint32_t pl[];
     __shared__ uint32_t wave_tot[kThreads / 64];
-    __shared__ uint64_t red[3][kThreads / 64][dd::kMaxWidths];
+    __shared__ uint64_t red1[kThreads / 64][dd::kMaxWidths];
+    __shared__ u128 red2[kThreads / 64][dd::kMaxWidths];
+    __shared__ uint32_t redm[kThreads / 64][dd::kMaxWidths];
+    __shared__ uint32_t vmax;
     const int d = blockIdx.y;
     const int seg = blockIdx.x;
     const int64_t s0 = static_cast<int64_t>(seg) * L;
-    const int n = L + W.w[W.n - 1] + 1;
-    load_prefix(in + static_cast<int64_t>(d) * nout, nout, s0 - 1, n, pl, wave_tot);
+    const int w_max = W.w[W.n - 1];
+    const int n = L + w_max + 1;
+    if (threadIdx.x == 0) vmax = 0;
+    load_prefix(in + static_cast<int64_t>(d) * nout, nout, s0 - 1, n, pl, wave_tot, &vmax);
     const int npos = static_cast<int>(min<int64_t>(L, nbx - s0));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool small = static_cast<uint64_t>(vmax) * static_cast<uint64_t>(w_max) < (uint64_t(1) << 26);
     for (int wi = 0; wi < W.n; ++wi) {
-        const int w = W.w[wi];
-        uint64_t s1 = 0, s2lo = 0, s2hi = 0;
-        for (int i = threadIdx.x; i < npos; i += kThreads) {
-            const uint32_t b = pl[i + 1 + w] - pl[i + 1];
-            s1 += b;
-            const uint64_t sq = static_cast<uint64_t>(b) * b;
-            s2lo += sq;
-            s2hi += (s2lo < sq) ? 1u : 0u;
-        }
-        // s2 = s2hi:s2lo; reduce lo with carries folded into hi.
-        s1 = wave_sum_u64(s1);
-        const uint64_t lo_lo = wave_sum_u64(s2lo & 0xFFFFFFFFull);
-        const uint64_t lo_hi = wave_sum_u64(s2lo >> 32);
-        s2hi = wave_sum_u64(s2hi);
+        uint64_t s1;
+        u128 s2;
+        uint32_t mx;
+        if (small)
+            width_sums<true>(pl, npos, W.w[wi], &s1, &s2, &mx);
+        else
+            width_sums<false>(pl, npos, W.w[wi], &s1, &s2, &mx);
         if (lane == 0) {
-            const u128 tot = static_cast<u128>(lo_lo) + (static_cast<u128>(lo_hi) << 32) +
-                             (static_cast<u128>(s2hi) << 64);
-            red[0][wave][wi] = s1;
-            red[1][wave][wi] = static_cast<uint64_t>(tot);
-            red[2][wave][wi] = static_cast<uint64_t>(tot >> 64);
+            red1[wave][wi] = s1;
+            red2[wave][wi] = s2;
+            redm[wave][wi] = mx;
         }
     }
     __syncthreads();
@@ -278,14 +315,17 @@ __global__ __launch_bounds__(kThreads) void boxcar_stats_kernel(const T* __restr
         const int wi = threadIdx.x;
         uint64_t s1 = 0;
         u128 s2 = 0;
+        uint32_t mx = 0;
         for (int v = 0; v < kThreads / 64; ++v) {
-            s1 += red[0][v][wi];
-            s2 += static_cast<u128>(red[1][v][wi]) | (static_cast<u128>(red[2][v][wi]) << 64);
+            s1 += red1[v][wi];
+            s2 += red2[v][wi];
+            mx = max(mx, redm[v][wi]);
         }
         const int64_t idx = (static_cast<int64_t>(wi) * gridDim.y + d) * nseg + seg;
         ws.part_s1[idx] = s1;
         ws.part_s2lo[idx] = static_cast<uint64_t>(s2);
         ws.part_s2hi[idx] = static_cast<uint64_t>(s2 >> 64);
+        ws.part_max[idx] = mx;
     }
 }
 
@@ -344,9 +384,12 @@ __global__ __launch_bounds__(kThreads) void peaks_count_kernel(const T* __restri
     const int d = blockIdx.y;
     const int seg = blockIdx.x;
     const int ndm = gridDim.y;
-    // Skip the scan when no series of this DM can have events.
+    // Skip the scan when no width of this (DM, segment) reaches its cut.
     bool any = false;
-    for (int wi = 0; wi < W.n; ++wi) any |= ws.thr32[wi * ndm + d] != 0xFFFFFFFFu;
+    for (int wi = 0; wi < W.n; ++wi) {
+        const int64_t idx = (static_cast<int64_t>(wi) * ndm + d) * nseg + seg;
+        any |= ws.part_max[idx] >= ws.thr32[wi * ndm + d];
+    }
     if (!any) {
         if (threadIdx.x < W.n)
             ws.counts[(static_cast<int64_t>(threadIdx.x) * ndm + d) * nseg + seg] = 0;
@@ -360,7 +403,7 @@ __global__ __launch_bounds__(kThreads) void peaks_count_kernel(const T* __restri
     const int lane = threadIdx.x & 63;
     for (int wi = 0; wi < W.n; ++wi) {
         const uint32_t thr = ws.thr32[wi * ndm + d];
-        if (thr == 0xFFFFFFFFu) continue;
+        if (ws.part_max[(static_cast<int64_t>(wi) * ndm + d) * nseg + seg] < thr) continue;
         const int w = W.w[wi];
         uint32_t c = 0;
         for (int i = threadIdx.x; i < npos; i += kThreads) {
@@ -551,6 +594,7 @@ PeaksLayout peaks_layout(int ndm, int64_t nout, const Widths& W) {
     lay.o_part_s1 = take(lay.ncounts * 8);
     lay.o_part_s2lo = take(lay.ncounts * 8);
     lay.o_part_s2hi = take(lay.ncounts * 8);
+    lay.o_part_max = take(lay.ncounts * 4);
     lay.o_s1 = take(lay.nseries * 8);
     lay.o_s2lo = take(lay.nseries * 8);
     lay.o_s2hi = take(lay.nseries * 8);
@@ -571,6 +615,7 @@ PeaksWs peaks_ws(void* base, const PeaksLayout& lay) {
     ws.part_s1 = reinterpret_cast<uint64_t*>(b + lay.o_part_s1);
     ws.part_s2lo = reinterpret_cast<uint64_t*>(b + lay.o_part_s2lo);
     ws.part_s2hi = reinterpret_cast<uint64_t*>(b + lay.o_part_s2hi);
+    ws.part_max = reinterpret_cast<uint32_t*>(b + lay.o_part_max);
     ws.s1 = reinterpret_cast<uint64_t*>(b + lay.o_s1);
     ws.s2lo = reinterpret_cast<uint64_t*>(b + lay.o_s2lo);
     ws.s2hi = reinterpret_cast<uint64_t*>(b + lay.o_s2hi);

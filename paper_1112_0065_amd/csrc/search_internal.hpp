@@ -24,6 +24,7 @@ struct PeaksWs {
     uint64_t* part_s1;     // [nw][ndm][nseg]
     uint64_t* part_s2lo;   // [nw][ndm][nseg]
     uint64_t* part_s2hi;   // [nw][ndm][nseg]
+    uint32_t* part_max;    // [nw][ndm][nseg] largest B of the segment
     uint64_t* s1;          // [nw][ndm]
     uint64_t* s2lo;        // [nw][ndm]
     uint64_t* s2hi;        // [nw][ndm]
@@ -43,7 +44,7 @@ struct PeaksLayout {
     int64_t nseries;
     int64_t ncounts;
     int nchunks;
-    size_t o_part_s1, o_part_s2lo, o_part_s2hi, o_s1, o_s2lo, o_s2hi, o_thr, o_thr32, o_sqrt_d,
+    size_t o_part_s1, o_part_s2lo, o_part_s2hi, o_part_max, o_s1, o_s2lo, o_s2hi, o_thr, o_thr32, o_sqrt_d,
         o_counts, o_offs, o_chunk, o_total;
     size_t bytes;
 };
