@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=128)
     ap.add_argument("--out-i32", action="store_true", help="int32 series instead of uint16")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: every beam and DM trial of this workload fits "
@@ -131,6 +133,16 @@ def main():
             t_ded.append(ev[1].elapsed_time(ev[2]))
             t_pk.append(ev[2].elapsed_time(ev[3]))
 
+    if args.calib_copy_mib:
+        # a plain copy of known size: what the HBM counters read for it
+        # calibrates the traffic of the kernels above
+        src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()

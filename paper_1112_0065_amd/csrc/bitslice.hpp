@@ -24,6 +24,16 @@
 #endif
 #endif
 
+// Three-input bit operations of a full adder: on gfx950 each is one
+// v_bitop3_b32 (truth tables 0x96 = odd parity, 0xE8 = majority).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define BS_XOR3(a, b, c) __builtin_amdgcn_bitop3_b32((a), (b), (c), 0x96)
+#define BS_MAJ3(a, b, c) __builtin_amdgcn_bitop3_b32((a), (b), (c), 0xE8)
+#else
+#define BS_XOR3(a, b, c) ((a) ^ (b) ^ (c))
+#define BS_MAJ3(a, b, c) (((a) & (b)) | ((c) & ((a) ^ (b))))
+#endif
+
 #include "csa_tree.inc"
 
 namespace bs {

@@ -46,6 +46,7 @@ struct BeamArgs {
     const int32_t* skew;     // per DM block, for the tile's block size
     void* out;               // [ndm][nout]
     int n_dm_blocks;
+    int tile_words;          // T/32 + 1 of the launch's tile shape
     int64_t item_begin;      // first work item of this beam in a batch
     int64_t n_items;         // time tiles x DM blocks
 };

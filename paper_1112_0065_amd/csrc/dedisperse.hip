@@ -72,7 +72,10 @@ __device__ __forceinline__ void process_item(const dd::BeamArgs& a, int tile, in
     constexpr int T = 2048 * G;
     const int64_t T0 = static_cast<int64_t>(tile) * T;
     const int d_lo = dblk * ND;
-    const int stride = T / 32 + 1 + a.skew[dblk];
+    // words per LDS channel row; T/32 + 1 arrives as a kernel argument so that
+    // the compiler keeps each channel's row offset a single scalar and the
+    // groups' reads fold into the LDS instructions' immediate offsets
+    const int stride = a.tile_words + a.skew[dblk];
     const int64_t w_base = T0 >> 5;
     const int32_t* dlo_row = a.delays + static_cast<int64_t>(d_lo) * a.nchans;
 
@@ -295,6 +298,7 @@ BeamArgs beam_args(const dedisp_plan_s* p, const uint2* words, int64_t nwords, i
     a.out = out;
     a.n_dm_blocks = (p->ndm + cfg.dms_per_block - 1) / cfg.dms_per_block;
     const int64_t T = 2048 * cfg.groups;
+    a.tile_words = static_cast<int>(T / 32 + 1);
     a.item_begin = 0;
     a.n_items = ((nout + T - 1) / T) * a.n_dm_blocks;
     return a;
