@@ -80,6 +80,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=128)
     ap.add_argument("--out-i32", action="store_true", help="int32 series instead of uint16")
+    ap.add_argument("--no-multibeam", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-chunks", type=int, default=3, help="chunks per beam when streaming")
+    ap.add_argument("--serve-speed", type=float, default=1.0,
+                    help="arrival rate as a multiple of real time")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -199,7 +204,129 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    del out, ws, pws, evb, inp
+    torch.cuda.empty_cache()
+    if not args.no_multibeam:
+        print("13-beam batch ...", file=sys.stderr, flush=True)
+        rec["multibeam"] = bench_multibeam(args)
+        rec["rtf_13beam"] = rec["multibeam"]["rtf_batch"]
+    if not args.no_serve:
+        print("13-beam streaming at the real-time rate ...", file=sys.stderr, flush=True)
+        rec["serve"] = bench_serve(args)
+        rec["p99_chunk_latency_s"] = rec["serve"]["p99_s"]
     print(json.dumps(rec), flush=True)
+
+
+def bench_multibeam(args):
+    """13 beams of uneven length (2^17 + 2^15 b samples) and DM range (max
+    500 + 125 ((5b) mod 13)), 1200 trials each: one persistent launch in a HIP
+    graph (dedisp_batch_execute) against 13 sequential single-beam calls.
+    Real-time factor = total beam-seconds / wall time."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1112_0065_amd import _lib as L
+
+    shapes = synth.multibeam_shapes()
+    nmax = max(n for n, _ in shapes)
+    pool = synth.fast_chunk(300, nmax, npulses=20)      # beam b reads a prefix of it
+    plans, ins, outs, evs, ns = [], [], [], [], []
+    widths = [1 << i for i in range(10)]
+    for b, (n, dm_max) in enumerate(shapes):
+        p = L.dedisp_plan_create(1024, synth.F_TOP, synth.DF_SURVEY, synth.TSAMP,
+                                 synth.dm_list_expm1(1200, dm_max))
+        plans.append(p)
+        ins.append(torch.from_numpy(pool[: n * 256]).to("cuda"))
+        outs.append(torch.empty((1200, n - p.max_delay), dtype=torch.int16, device="cuda"))
+        evs.append(torch.empty((1 << 20) * 40, dtype=torch.uint8, device="cuda"))
+        ns.append(n)
+    cap = [1 << 20] * len(plans)
+    batch = L.dedisp_batch_create(plans, widths, 6.0, out_u16=True)
+    tile, grid, _ = L.dedisp_batch_info(batch)
+    reps = max(2, args.steps // 4)
+    L.dedisp_batch_execute(batch, ins, ns, outs, evs, cap)      # capture + warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        counts = L.dedisp_batch_execute(batch, ins, ns, outs, evs, cap)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    # the same work as 13 sequential single-beam calls
+    wss = [torch.empty(L.dedisp_workspace_bytes(p, n), dtype=torch.uint8, device="cuda")
+           for p, n in zip(plans, ns)]
+    pwss = [torch.empty(L.find_peaks_workspace_bytes(1200, n - p.max_delay, widths),
+                        dtype=torch.uint8, device="cuda") for p, n in zip(plans, ns)]
+
+    def sequential():
+        for b in range(len(plans)):
+            L.dedisp_execute(plans[b], ins[b], ns[b], outs[b], wss[b])
+            L.find_peaks(outs[b], 1200, ns[b] - plans[b].max_delay, widths, 6.0, evs[b], cap[b],
+                         pwss[b])
+
+    sequential()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sequential()
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / reps
+    beam_s = sum(ns) * synth.TSAMP
+    dm_samples = sum(1200 * (n - p.max_delay) for p, n in zip(plans, ns))
+    return {"beams": len(plans), "beam_seconds": beam_s, "tile": list(tile), "grid": grid,
+            "ms_batch": t_batch * 1e3, "ms_sequential": t_seq * 1e3,
+            "rtf_batch": beam_s / t_batch, "rtf_sequential": beam_s / t_seq,
+            "dm_trial_samples_per_s_batch": dm_samples / t_batch,
+            "events": int(sum(counts)),
+            "data": "fast 2-bit noise with 20 dispersed pulses; beam b reads a prefix"}
+
+
+def bench_serve(args):
+    """13 beams streaming chunks of 2^17 samples (8.39 s) at the real-time
+    rate, beam b starting b/13 of a chunk late; 1200 trials to DM 1000;
+    HBM budget 32 GiB.  Latency = completion minus arrival of the chunk's last
+    sample."""
+    import numpy as np
+
+    import synth
+    from paper_1112_0065_amd import _lib as L
+
+    C = 1 << 17
+    nchunks = args.serve_chunks
+    speed = args.serve_speed
+    payloads = [synth.fast_chunk(400 + k, C, npulses=5) for k in range(4)]
+    dms = synth.dm_list_expm1(1200, 1000.0)
+    plans = [L.dedisp_plan_create(1024, synth.F_TOP, synth.DF_SURVEY, synth.TSAMP, dms)
+             for _ in range(13)]
+    widths = [1 << i for i in range(10)]
+    srv = L.dedisp_serve_create(plans, C, widths, 6.0, 32 << 30)
+    period_ns = C * synth.TSAMP * 1e9 / speed
+    sched = sorted((b * period_ns / 13 + (k + 1) * period_ns, b, k)
+                   for b in range(13) for k in range(nchunks))
+    t_start = L.dedisp_now_ns()
+    done = []
+    busy = 0
+    for due, b, k in sched:
+        while L.dedisp_now_ns() - t_start < due:
+            done += L.dedisp_serve_poll(srv, 64, 0)
+            time.sleep(0.0005)
+        arrival = t_start + int(due)
+        while not L.dedisp_serve_submit(srv, b, k, payloads[(b + k) % 4], arrival):
+            busy += 1
+            time.sleep(0.0005)
+    while len(done) < len(sched):
+        done += L.dedisp_serve_poll(srv, 64, 100)
+    st = L.dedisp_serve_stats(srv)
+    wall = (L.dedisp_now_ns() - t_start) * 1e-9
+    srv.close()
+    late = sum(1 for r in done if r["flags"] & L.CHUNK_LATE)
+    return {"beams": 13, "chunks": len(done), "chunk_samples": C, "speed_vs_real_time": speed,
+            "deadline_s": st["deadline_ns"] * 1e-9 / speed, "p50_s": st["p50_ns"] * 1e-9,
+            "p99_s": st["p99_ns"] * 1e-9, "max_s": st["max_ns"] * 1e-9,
+            "deadline_misses": late if speed == 1.0 else None,
+            "batches": st["batches"], "mean_batch": st["mean_batch"], "max_batch": st["max_batch"],
+            "slots": st["slots"], "busy_retries": busy, "wall_s": wall,
+            "data": "4 fast-noise chunk payloads cycled over beams and sequence numbers"}
 
 
 if __name__ == "__main__":

@@ -275,7 +275,116 @@ __device__ __forceinline__ void width_sums(const uint32_t* pl, int npos, int w, 
     *mx_out = mx;
 }
 
-template <typename T>
+// The common case -- a full segment of kPerThread * 256 positions and small
+// values -- with every loop unrolled: each thread keeps its 32 running-sum
+// bases in registers and reads one running sum per (width, position).
+constexpr int kPerThread = 32;
+
+__device__ __forceinline__ void width_sums_full(const uint32_t* pl, const uint32_t (&p0)[kPerThread],
+                                                int w, uint64_t* s1_out, u128* s2_out,
+                                                uint32_t* mx_out) {
+    uint32_t s1 = 0, mx = 0;   // 32 terms below 2^26: no overflow
+    uint64_t s2 = 0;
+    const uint32_t* q = pl + 1 + w + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < kPerThread; ++j) {
+        const uint32_t b = q[j * kThreads] - p0[j];
+        s1 += b;
+        s2 += static_cast<uint64_t>(b) * b;
+        mx = max(mx, b);
+    }
+    *s1_out = wave_sum_u64(s1);
+    *s2_out = wave_sum_u64(s2);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mx = max(mx, static_cast<uint32_t>(__shfl_xor(mx, o, 64)));
+    *mx_out = mx;
+}
+
+// Fast path of a full segment with small values and NW (compile-time)
+// widths: positions outer, widths inner, every partial sum in registers, then
+// one block reduction through LDS (which the running sums no longer need).
+template <int NW>
+__device__ __forceinline__ void stats_full_nw(uint32_t* pl, const dd::Widths& W, uint64_t* s1_out,
+                                              u128* s2_out, uint32_t* mx_out) {
+    uint32_t s1[NW], mx[NW];
+    uint64_t s2[NW];
+    int woff[NW];
+#pragma unroll
+    for (int wi = 0; wi < NW; ++wi) {
+        s1[wi] = 0;
+        mx[wi] = 0;
+        s2[wi] = 0;
+        woff[wi] = W.w[wi];
+    }
+    const uint32_t* base = pl + 1 + threadIdx.x;
+#pragma unroll 4
+    for (int j = 0; j < kPerThread; ++j) {
+        const uint32_t p0 = base[j * kThreads];
+#pragma unroll
+        for (int wi = 0; wi < NW; ++wi) {
+            const uint32_t b = base[j * kThreads + woff[wi]] - p0;
+            s1[wi] += b;
+            s2[wi] += static_cast<uint64_t>(b) * b;
+            mx[wi] = max(mx[wi], b);
+        }
+    }
+    __syncthreads();   // the running sums are no longer needed: reuse pl
+    uint64_t* r = reinterpret_cast<uint64_t*>(pl);
+    const int t = threadIdx.x;
+    // squares: [NW][256] -> 16 partials per width -> 1
+#pragma unroll
+    for (int wi = 0; wi < NW; ++wi) r[wi * kThreads + t] = s2[wi];
+    __syncthreads();
+    uint64_t acc = 0;
+    if (t < NW * 16) {
+        const uint64_t* q = r + (t / 16) * kThreads + (t % 16) * 16;
+        for (int k = 0; k < 16; ++k) acc += q[k];
+    }
+    __syncthreads();
+    if (t < NW * 16) r[t] = acc;
+    __syncthreads();
+    if (t < NW) {
+        uint64_t v = 0;
+        for (int k = 0; k < 16; ++k) v += r[t * 16 + k];
+        s2_out[t] = v;
+    }
+    __syncthreads();
+    // sums and maxima
+#pragma unroll
+    for (int wi = 0; wi < NW; ++wi) {
+        r[wi * kThreads + t] = s1[wi];
+        pl[2 * NW * kThreads + wi * kThreads + t] = mx[wi];
+    }
+    __syncthreads();
+    uint64_t a1 = 0;
+    uint32_t am = 0;
+    if (t < NW * 16) {
+        const uint64_t* q = r + (t / 16) * kThreads + (t % 16) * 16;
+        const uint32_t* qm = pl + 2 * NW * kThreads + (t / 16) * kThreads + (t % 16) * 16;
+        for (int k = 0; k < 16; ++k) {
+            a1 += q[k];
+            am = max(am, qm[k]);
+        }
+    }
+    __syncthreads();
+    if (t < NW * 16) {
+        r[t] = a1;
+        pl[2 * NW * kThreads + t] = am;
+    }
+    __syncthreads();
+    if (t < NW) {
+        uint64_t v = 0;
+        uint32_t m = 0;
+        for (int k = 0; k < 16; ++k) {
+            v += r[t * 16 + k];
+            m = max(m, pl[2 * NW * kThreads + t * 16 + k]);
+        }
+        s1_out[t] = v;
+        mx_out[t] = m;
+    }
+}
+
+template <typename T, int NW>
 __global__ __launch_bounds__(kThreads) void boxcar_stats_kernel(const T* __restrict__ in,
                                                                 int64_t nout, int64_t nbx,
                                                                 dd::Widths W, int L, int nseg,
@@ -296,6 +405,24 @@ __global__ __launch_bounds__(kThreads) void boxcar_stats_kernel(const T* __restr
     const int npos = static_cast<int>(min<int64_t>(L, nbx - s0));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool small = static_cast<uint64_t>(vmax) * static_cast<uint64_t>(w_max) < (uint64_t(1) << 26);
+    const bool full = small && npos == kPerThread * kThreads;
+    constexpr int NWS = NW > 0 ? NW : 1;
+    if (NW > 0 && full) {
+        __shared__ uint64_t f1[NWS];
+        __shared__ u128 f2[NWS];
+        __shared__ uint32_t fm[NWS];
+        stats_full_nw<NWS>(pl, W, f1, f2, fm);
+        __syncthreads();
+        if (threadIdx.x < NW) {
+            const int wi = threadIdx.x;
+            const int64_t idx = (static_cast<int64_t>(wi) * gridDim.y + d) * nseg + seg;
+            ws.part_s1[idx] = f1[wi];
+            ws.part_s2lo[idx] = static_cast<uint64_t>(f2[wi]);
+            ws.part_s2hi[idx] = static_cast<uint64_t>(f2[wi] >> 64);
+            ws.part_max[idx] = fm[wi];
+        }
+        return;
+    }
     for (int wi = 0; wi < W.n; ++wi) {
         uint64_t s1;
         u128 s2;
@@ -462,7 +589,43 @@ __global__ __launch_bounds__(kThreads) void scan_add_kernel(int64_t* __restrict_
     if (i < n) offs[i] += chunk_tot[i / kScanChunk];
 }
 
-// Pass 4: write the events of segments that have any.
+// Walk the run that starts at t with boxcar value b (sliding window sum) and
+// write its event record.
+template <typename T>
+__device__ __forceinline__ void write_event(const T* __restrict__ row, int64_t nbx, int w, int wi, int d,
+                                            int64_t t, uint32_t b, uint32_t thr, uint64_t s1, double sqrt_d,
+                                            dedisp_event* __restrict__ out) {
+    int64_t te = t, tp = t, u = t;
+    uint32_t cur = b, best = b;
+    while (u + 1 < nbx) {
+        const uint32_t nb = cur + static_cast<uint32_t>(row[u + w]) - static_cast<uint32_t>(row[u]);
+        if (nb < thr) break;
+        ++u;
+        cur = nb;
+        te = u;
+        if (nb > best) {
+            best = nb;
+            tp = u;
+        }
+    }
+    const int64_t lval = static_cast<int64_t>(nbx) * best - static_cast<int64_t>(s1);
+    dedisp_event ev;
+    ev.width_idx = wi;
+    ev.dm_idx = d;
+    ev.t_start = t;
+    ev.t_end = te;
+    ev.t_peak = tp;
+    ev.b_peak = static_cast<int32_t>(best);
+    ev.snr = static_cast<float>(static_cast<double>(lval) / sqrt_d);
+    *out = ev;
+}
+
+// Pass 4: write the events of segments that have any.  The run starts of a
+// (width, DM, segment) are collected in LDS (any order), ranked by position
+// (they are few), and each is expanded by one thread at offset + rank;
+// segments with very many starts use block-wide scans in position order.
+constexpr int kMaxStarts = 1024;
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void peaks_write_kernel(const T* __restrict__ in,
                                                                int64_t nout, int64_t nbx,
@@ -472,6 +635,9 @@ __global__ __launch_bounds__(kThreads) void peaks_write_kernel(const T* __restri
                                                                int64_t capacity) {
     extern __shared__ uint32_t pl[];
     __shared__ uint32_t wave_tot[kThreads / 64];
+    __shared__ int starts[kMaxStarts];
+    __shared__ int nstart;
+    __shared__ uint32_t slab_total;
     const int d = blockIdx.y;
     const int seg = blockIdx.x;
     const int ndm = gridDim.y;
@@ -486,54 +652,55 @@ __global__ __launch_bounds__(kThreads) void peaks_write_kernel(const T* __restri
     const int npos = static_cast<int>(min<int64_t>(L, nbx - s0));
     for (int wi = 0; wi < W.n; ++wi) {
         const int64_t cidx = (static_cast<int64_t>(wi) * ndm + d) * nseg + seg;
-        if (ws.counts[cidx] == 0) continue;
+        const uint32_t cnt = ws.counts[cidx];
+        if (cnt == 0) continue;
         const int sidx = wi * ndm + d;
         const uint32_t thr = ws.thr32[sidx];
         const int w = W.w[wi];
-        int64_t rank = ws.offs[cidx];
-        for (int base = 0; base < npos; base += kThreads) {
-            const int i = base + threadIdx.x;
-            bool start = false;
-            uint32_t b = 0;
-            if (i < npos) {
-                b = pl[i + 1 + w] - pl[i + 1];
+        const int64_t off = ws.offs[cidx];
+        const uint64_t s1 = ws.s1[sidx];
+        const double sq = ws.sqrt_d[sidx];
+        if (cnt <= kMaxStarts) {
+            if (threadIdx.x == 0) nstart = 0;
+            __syncthreads();
+            for (int i = threadIdx.x; i < npos; i += kThreads) {
+                const uint32_t b = pl[i + 1 + w] - pl[i + 1];
                 const bool prev = (s0 + i > 0) && (pl[i + w] - pl[i] >= thr);
-                start = b >= thr && !prev;
-            }
-            const uint32_t ex = block_exclusive_scan(start ? 1u : 0u, wave_tot);
-            if (start) {
-                const int64_t e = rank + ex;
-                if (e < capacity) {
-                    // walk the run with a sliding window sum
-                    int64_t t = s0 + i, te = t, tp = t;
-                    uint32_t cur = b, best = b;
-                    while (t + 1 < nbx) {
-                        const uint32_t nb = cur + static_cast<uint32_t>(row[t + w]) -
-                                            static_cast<uint32_t>(row[t]);
-                        if (nb < thr) break;
-                        ++t;
-                        cur = nb;
-                        te = t;
-                        if (nb > best) { best = nb; tp = t; }
-                    }
-                    const int64_t lval = static_cast<int64_t>(nbx) * best - static_cast<int64_t>(ws.s1[sidx]);
-                    dedisp_event ev;
-                    ev.width_idx = wi;
-                    ev.dm_idx = d;
-                    ev.t_start = s0 + i;
-                    ev.t_end = te;
-                    ev.t_peak = tp;
-                    ev.b_peak = static_cast<int32_t>(best);
-                    ev.snr = static_cast<float>(static_cast<double>(lval) / ws.sqrt_d[sidx]);
-                    events[e] = ev;
+                if (b >= thr && !prev) {
+                    const int k = atomicAdd(&nstart, 1);
+                    if (k < kMaxStarts) starts[k] = i;
                 }
             }
-            // total starts in this slab (last thread's exclusive + own)
-            __shared__ uint32_t slab_total;
-            if (threadIdx.x == kThreads - 1) slab_total = ex + (start ? 1u : 0u);
             __syncthreads();
-            rank += slab_total;
+            const int m = min(nstart, kMaxStarts);
+            for (int k = threadIdx.x; k < m; k += kThreads) {
+                const int i = starts[k];
+                int rank = 0;
+                for (int q = 0; q < m; ++q) rank += starts[q] < i;
+                const int64_t e = off + rank;
+                if (e < capacity)
+                    write_event(row, nbx, w, wi, d, s0 + i, pl[i + 1 + w] - pl[i + 1], thr, s1, sq, &events[e]);
+            }
             __syncthreads();
+        } else {
+            int64_t rank = off;
+            for (int base = 0; base < npos; base += kThreads) {
+                const int i = base + threadIdx.x;
+                bool start = false;
+                uint32_t b = 0;
+                if (i < npos) {
+                    b = pl[i + 1 + w] - pl[i + 1];
+                    const bool prev = (s0 + i > 0) && (pl[i + w] - pl[i] >= thr);
+                    start = b >= thr && !prev;
+                }
+                const uint32_t ex = block_exclusive_scan(start ? 1u : 0u, wave_tot);
+                if (start && rank + ex < capacity)
+                    write_event(row, nbx, w, wi, d, s0 + i, b, thr, s1, sq, &events[rank + ex]);
+                if (threadIdx.x == kThreads - 1) slab_total = ex + (start ? 1u : 0u);
+                __syncthreads();
+                rank += slab_total;
+                __syncthreads();
+            }
         }
     }
 }
@@ -574,6 +741,41 @@ hipError_t launch_boxcar(const void* in, int in_u16, int ndm, int64_t nout, cons
                            static_cast<const int32_t*>(in), nout, nbx, W, dm_first, L, out, dm_count);
     }
     return hipGetLastError();
+}
+
+template <typename T, int NW>
+hipError_t launch_stats_t(const void* in, int64_t nout, const Widths& W, const PeaksLayout& lay,
+                          const PeaksWs& ws, dim3 grid, size_t lds, hipStream_t s) {
+    auto kern = boxcar_stats_kernel<T, NW>;
+    hipError_t e = set_lds_limit(reinterpret_cast<const void*>(kern), lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, s, static_cast<const T*>(in), nout, lay.nbx,
+                       W, lay.L, lay.nseg, ws);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stats_w(const void* in, int64_t nout, const Widths& W, const PeaksLayout& lay,
+                          const PeaksWs& ws, dim3 grid, size_t lds, hipStream_t s) {
+    // the register fast path reuses the running-sum area (L + w_max + 1 words)
+    // for its reduction (3 * NW * 256 words)
+    const int w_max = W.w[W.n - 1];
+    const int nw = (lay.L == kPerThread * kThreads && W.n <= 16 &&
+                    3 * W.n * kThreads <= lay.L + w_max + 1) ? W.n : 0;
+    switch (nw) {
+#define DD_NW(N) case N: return launch_stats_t<T, N>(in, nout, W, lay, ws, grid, lds, s);
+        DD_NW(1) DD_NW(2) DD_NW(3) DD_NW(4) DD_NW(5) DD_NW(6) DD_NW(7) DD_NW(8)
+        DD_NW(9) DD_NW(10) DD_NW(11) DD_NW(12) DD_NW(13) DD_NW(14) DD_NW(15) DD_NW(16)
+#undef DD_NW
+        default: return launch_stats_t<T, 0>(in, nout, W, lay, ws, grid, lds, s);
+    }
+}
+
+hipError_t launch_stats(const void* in, int in_u16, int64_t nout, const Widths& W,
+                        const PeaksLayout& lay, const PeaksWs& ws, dim3 grid, size_t lds,
+                        hipStream_t s) {
+    return in_u16 ? launch_stats_w<uint16_t>(in, nout, W, lay, ws, grid, lds, s)
+                  : launch_stats_w<int32_t>(in, nout, W, lay, ws, grid, lds, s);
 }
 
 PeaksLayout peaks_layout(int ndm, int64_t nout, const Widths& W) {
@@ -635,16 +837,7 @@ hipError_t launch_peaks_count(const void* in, int in_u16, int ndm, int64_t nout,
     const int w_max = W.w[W.n - 1];
     const size_t lds = peaks_lds_bytes(lay.L, w_max);
     const dim3 grid(static_cast<unsigned>(lay.nseg), static_cast<unsigned>(ndm));
-    if (in_u16) {
-        set_lds_limit(reinterpret_cast<const void*>(boxcar_stats_kernel<uint16_t>), lds);
-        hipLaunchKernelGGL(boxcar_stats_kernel<uint16_t>, grid, dim3(kThreads), lds, s,
-                           static_cast<const uint16_t*>(in), nout, lay.nbx, W, lay.L, lay.nseg, ws);
-    } else {
-        set_lds_limit(reinterpret_cast<const void*>(boxcar_stats_kernel<int32_t>), lds);
-        hipLaunchKernelGGL(boxcar_stats_kernel<int32_t>, grid, dim3(kThreads), lds, s,
-                           static_cast<const int32_t*>(in), nout, lay.nbx, W, lay.L, lay.nseg, ws);
-    }
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_stats(in, in_u16, nout, W, lay, ws, grid, lds, s);
     if (e != hipSuccess) return e;
     const int nser = static_cast<int>(lay.nseries);
     hipLaunchKernelGGL(series_threshold_kernel, dim3((nser + kThreads - 1) / kThreads), dim3(kThreads),

@@ -280,6 +280,109 @@ def make_multibeam_beam(b: int) -> Filterbank:
     return make_beam(300 + b, nsamps, dm_max, 10, name=f"multibeam_b{b}")
 
 
+@dataclasses.dataclass
+class Impulse:
+    t: int          # first sample
+    width: int      # samples
+    amp: float      # added to every channel (float domain, units of sigma)
+
+
+def make_rfi_beam(seed: int, nsamps: int = 1 << 17, dm_max: float = 1000.0,
+                  npulses: int = 8, nchans: int = 1024, ndm: int = 1200,
+                  impulse_rate: float = 0.5, name: str = "rfi_beam") -> Filterbank:
+    """Survey-shaped beam with dispersed pulses and three kinds of
+    interference (the paper's section 2.1 names interference as the main
+    source of false events; its forms here are a model):
+      * zero-DM broadband impulses: Poisson, `impulse_rate` per second,
+        width U{1..8} samples, amplitude U(2, 6) sigma in every channel;
+      * persistent narrowband channels: 5% of channels with +1 sigma offset
+        and twice the noise sigma;
+      * 50 Hz periodic interference: 16-sample pulses every 312.5 samples
+        (start rounded half away from zero) on a contiguous 10% band at
+        1 sigma, active inside one random 2 s window.
+    Pulses follow the survey recipe (DM U(0, dm_max), width log-uniform
+    1..500 samples, nominal S/N U(6, 30))."""
+    rng_n, rng_p = _streams(seed)
+    dm_list = dm_list_expm1(ndm, dm_max)
+    df = -400.0 / nchans
+    pulses = _snr_pulses(rng_p, npulses, nchans, nsamps, 0.0, dm_max, F_TOP, df, TSAMP)
+    offs = [sky_arrival_offsets(nchans, F_TOP, df, TSAMP, p.dm) for p in pulses]
+    dur = nsamps * TSAMP
+    nimp = int(rng_p.poisson(impulse_rate * dur))
+    imps = [Impulse(int(rng_p.integers(0, nsamps - 8)), int(rng_p.integers(1, 9)),
+                    float(rng_p.uniform(2.0, 6.0))) for _ in range(nimp)]
+    nb = rng_p.choice(nchans, size=max(1, nchans // 20), replace=False)
+    band0 = int(rng_p.integers(0, nchans - nchans // 10))
+    band = np.arange(band0, band0 + nchans // 10)
+    win0 = int(rng_p.integers(0, max(1, nsamps - int(2.0 / TSAMP))))
+    win1 = min(nsamps, win0 + int(2.0 / TSAMP))
+    starts = []
+    k = 0
+    while True:
+        s = math.floor(312.5 * k + 0.5)
+        if s >= nsamps:
+            break
+        if win0 <= s < win1:
+            starts.append(s)
+        k += 1
+    pulse_inj = _float_pulse_injector(pulses, offs)
+
+    def inject(x, t_lo):
+        n = x.shape[0]
+        x[:, nb] = x[:, nb] * 2.0 + 1.0
+        pulse_inj(x, t_lo)
+        for im in imps:
+            lo, hi = max(im.t, t_lo), min(im.t + im.width, t_lo + n)
+            if lo < hi:
+                x[lo - t_lo:hi - t_lo, :] += im.amp
+        for s in starts:
+            lo, hi = max(s, t_lo), min(s + 16, t_lo + n)
+            if lo < hi:
+                x[lo - t_lo:hi - t_lo, band] += 1.0
+
+    packed = _noise_levels(rng_n, nsamps, nchans, inject)
+    return Filterbank(name, seed, nchans, nsamps, F_TOP, df, TSAMP, dm_list,
+                      [1 << i for i in range(10)], 6.0, packed, pulses,
+                      rfi=dict(impulses=imps, narrowband=nb.tolist(), band=[band0, band0 + nchans // 10],
+                               periodic_window=[win0, win1]))
+
+
+def fast_levels(rng: np.random.Generator, nsamps: int, nchans: int) -> np.ndarray:
+    """2-bit levels with the quantiser's level probabilities (0.163543,
+    0.336457, 0.336457, 0.163543) drawn directly from 16-bit uniforms -- a
+    faster stand-in for quantised Gaussian noise, time-major [nsamps][nchans]."""
+    u = np.frombuffer(rng.bytes(2 * nsamps * nchans), dtype=np.uint16).reshape(nsamps, nchans)
+    q = (u >= 10718).astype(np.uint8)
+    q += (u >= 32768)
+    q += (u >= 54818)
+    return q
+
+
+def fast_chunk(seed: int, nsamps: int, nchans: int = 1024, f_top: float = F_TOP,
+               df: float = DF_SURVEY, npulses: int = 5, dm_max: float = 1000.0) -> np.ndarray:
+    """Packed chunk of fast-level noise with `npulses` dispersed boxcar pulses
+    (throughput inputs).  A pulse of width W and nominal S/N s raises the
+    level by one (capped at 3) along its sweep in a random fraction
+    f = s * 0.95 / (0.84 * sqrt(nchans * W)) of the channels (a +1 step adds
+    ~0.84 on average; one level's sigma is 0.95)."""
+    rng = np.random.default_rng(seed)
+    q = fast_levels(rng, nsamps, nchans)
+    for _ in range(npulses):
+        dm = float(rng.uniform(0, dm_max))
+        w = int(rng.integers(1, 65))
+        snr = float(rng.uniform(8.0, 30.0))
+        frac = min(1.0, snr * 0.95 / (0.84 * math.sqrt(nchans * w)))
+        chans = np.nonzero(rng.uniform(size=nchans) < frac)[0]
+        off = sky_arrival_offsets(nchans, f_top, df, TSAMP, dm)
+        if off.max() + w + 1 >= nsamps:
+            continue
+        t0 = int(rng.integers(0, nsamps - off.max() - w))
+        for c in chans:
+            seg = q[t0 + off[c]:t0 + off[c] + w, c]
+            np.minimum(seg + 1, 3, out=seg)
+    return pack_2bit(q)
+
+
 def make_tiny(seed: int, nchans: int, nsamps: int, dm_list: Sequence[float],
               f_top: float = F_TOP, df: float = -12.5, tsamp: float = TSAMP,
               widths: Sequence[int] = (1, 2, 4), snr_thresh: float = 3.0,

@@ -93,6 +93,7 @@ def test_find_peaks_thresholds_and_ties(k):
     series[5, :] = 7               # constant series: D = 0 for every width
     series[6, 3990:] = 30          # run touching the end
     series[7, :20] = 30            # run at the start
+    series[8, :] = np.tile([0, 11], 2000)   # ~2000 one-sample runs in one segment
     widths = [1, 2, 3, 8]
     bw = oracle.boxcar(series, widths)
     ref = oracle.find_events(bw, k)
