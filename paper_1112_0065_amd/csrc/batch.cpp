@@ -57,6 +57,7 @@ hipError_t launch_multi(const MultiItem* items, int n, const Widths& W, uint32_t
         const int64_t nout = it.nsamps - it.plan->max_delay;
         h_beams[i] = beam_args(it.plan, static_cast<const uint2*>(it.words), repack_words(it.nsamps),
                                nout, it.out, cfg);
+        if (!h_beams[i].offs) return hipErrorInvalidValue;   // table not built for this shape
         h_beams[i].item_begin = total;
         total += h_beams[i].n_items;
     }
@@ -161,6 +162,13 @@ extern "C" dedisp_status dedisp_batch_create(const dedisp_plan* plans, int32_t n
     if (b->grid < 1) {
         delete b;
         return fail(DEDISP_ERR_HIP, "occupancy query of the persistent kernel failed");
+    }
+    for (int i = 0; i < nbeams; ++i) {
+        dedisp_status sto = DEDISP_OK;
+        if (!dd::offset_table(plans[i], b->cfg, true, &sto)) {
+            delete b;
+            return sto;
+        }
     }
     hipError_t e = hipSuccess;
     b->words.assign(nbeams, nullptr);

@@ -6,6 +6,7 @@
 #include <atomic>
 #include <cstdarg>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -43,10 +44,12 @@ struct BeamArgs {
     int ndm;
     int64_t nout;
     const int32_t* delays;   // [ndm][nchans]
+    const uint32_t* offs;    // [ndm][nchans] LDS read offsets for the tile shape
     const int32_t* skew;     // per DM block, for the tile's block size
     void* out;               // [ndm][nout]
     int n_dm_blocks;
     int tile_words;          // T/32 + 1 of the launch's tile shape
+    int pitch;               // words per LDS row: tile_words + the largest block skew
     int64_t item_begin;      // first work item of this beam in a batch
     int64_t n_items;         // time tiles x DM blocks
 };
@@ -72,6 +75,14 @@ struct dedisp_plan_s {
     int32_t skew_max[kNumDmBlock] = {0, 0, 0, 0};
     // Tile shape chosen by the autotuner (dms << 16 | groups << 8 | stage), 0 = default.
     std::atomic<int> tuned{0};
+    // Per tile shape: the LDS read offset and funnel shift of every (trial,
+    // channel), built on first use of the shape (dd::offset_table).
+    struct OffsetTable {
+        int dms, groups, stage;
+        uint32_t* d;
+    };
+    mutable std::mutex tab_mu;
+    mutable std::vector<OffsetTable> tabs;
 };
 
 namespace dd {
@@ -97,6 +108,19 @@ void apply_env_cache(dedisp_plan_s* p);
 BeamArgs beam_args(const dedisp_plan_s* p, const uint2* words, int64_t nwords, int64_t nout,
                    void* out, const TileConfig& cfg);
 size_t tile_lds_bytes(const dedisp_plan_s* p, const TileConfig& cfg);
+int tile_pitch(const dedisp_plan_s* p, const TileConfig& cfg);
+// Device table of the tile shape, [ndm][nchans] entries
+//     ((c mod CS) * pitch + (delay[d][c] >> 5) - (delay[d_lo][c] >> 5)) * 8 << 5
+//   | (delay[d][c] & 31)
+// with d_lo the block's first trial and pitch = 64*G + 1 + (largest block
+// skew): the byte offset, in an LDS stage buffer, of the first word the trial
+// reads of channel c, and the shift within it.  Built (synchronously: hipMalloc + hipMemcpy) on first use of the
+// shape; `build` false only looks it up.  Returns nullptr on failure.
+const uint32_t* offset_table(const dedisp_plan_s* p, const TileConfig& cfg, bool build,
+                             dedisp_status* st = nullptr);
+// Free the tables of every shape not in `keep`; the shapes that have one.
+void drop_offset_tables(const dedisp_plan_s* p, const std::vector<TileConfig>& keep);
+std::vector<TileConfig> offset_table_shapes(const dedisp_plan_s* p);
 // Persistent multi-beam launch (beams: device array, item ranges filled).
 hipError_t launch_dedisperse_persistent(const BeamArgs* d_beams, int nbeams, int64_t total,
                                         int nl, int out_u16, const TileConfig& cfg, size_t lds,

@@ -10,8 +10,10 @@
 //   * channels are streamed in stages of CS channels: the block copies, per
 //     channel, the skewed window of words all its trials need into LDS
 //     (one coalesced load shared by the ND trials);
-//   * per (trial, channel) a lane reads two words per group, aligns them to
-//     the trial's delay with one funnel shift per plane, and adds the 32
+//   * per (trial, channel) a lane reads two words per group at an LDS offset
+//     taken from the plan's per-tile-shape offset table (one scalar load per
+//     channel; the table also carries the shift within the word), aligns them
+//     to the trial's delay with one funnel shift per plane, and adds the 32
 //     2-bit samples into a bit-sliced counter with carry-save adder trees:
 //     about 8 bit-operations add 32 samples (see gen_csa.py);
 //   * after the last stage the counter planes are transposed to integers in
@@ -24,6 +26,31 @@ namespace {
 
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
+
+// Read-only tables (delays, skews, beam descriptors) are read through the
+// constant address space: the loads stay scalar even after the output stores
+// of an earlier work item, which would otherwise force them onto the vector
+// memory path in the persistent kernel.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+    return (cptr<T>)p;
+}
+
+// Word-wise copy of a descriptor out of the constant address space.
+__device__ __forceinline__ dd::BeamArgs load_beam(cptr<dd::BeamArgs> p) {
+    static_assert(sizeof(dd::BeamArgs) % 4 == 0, "descriptor size");
+    constexpr int n = sizeof(dd::BeamArgs) / 4;
+    const cptr<uint32_t> w = (cptr<uint32_t>)p;
+    uint32_t tmp[n];
+#pragma unroll
+    for (int i = 0; i < n; ++i) tmp[i] = w[i];
+    dd::BeamArgs a;
+    __builtin_memcpy(&a, tmp, sizeof a);
+    return a;
+}
 
 template <int NL, int N>
 __device__ __forceinline__ void csa_add(uint32_t (&a)[NL], const uint32_t (&lo)[N],
@@ -41,30 +68,98 @@ DD_CSA_SPEC(16, 4) DD_CSA_SPEC(16, 8) DD_CSA_SPEC(16, 16) DD_CSA_SPEC(16, 32)
 
 // Accumulate channels [c, c+N) of the current stage for one trial into the
 // counters of its G groups.
+// The trial's offset-table row gives, per channel, the LDS byte offset of the
+// channel's first needed word (bits 5 and up) and the funnel shift (bits 0-4,
+// which is all the shift instruction reads).
 template <int NL, int G, int N>
-__device__ __forceinline__ void accumulate_chunk(uint32_t (&acc)[G][NL], const uint2* lds,
-                                                 const int32_t* __restrict__ drow,
-                                                 const int32_t* __restrict__ dlo_row, int c,
-                                                 int cl, int stride, int lane) {
+__device__ __forceinline__ void accumulate_chunk(uint32_t (&acc)[G][NL], const uint2* lds_lane,
+                                                 cptr<uint32_t> trow, int c) {
+    uint32_t e[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) e[k] = trow[c + k];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
+        // all N reads first, then the shifts: the reads' latencies overlap
+        uint4 w[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const uint2* p = reinterpret_cast<const uint2*>(
+                                 reinterpret_cast<const char*>(lds_lane) + (e[k] >> 5)) + 64 * g;
+            const uint2 w0 = p[0];
+            const uint2 w1 = p[1];
+            w[k] = make_uint4(w0.x, w0.y, w1.x, w1.y);
+        }
         uint32_t lo[N], hi[N];
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            const int dl = drow[c + k];
-            const int rel = (dl >> 5) - (dlo_row[c + k] >> 5);
-            const uint32_t r = static_cast<uint32_t>(dl & 31);
-            const uint2* p = lds + (cl + k) * stride + rel + lane + 64 * g;
-            const uint2 w0 = p[0];
-            const uint2 w1 = p[1];
-            lo[k] = bs::funnel(w1.x, w0.x, r);
-            hi[k] = bs::funnel(w1.y, w0.y, r);
+            lo[k] = bs::funnel(w[k].z, w[k].x, e[k]);
+            hi[k] = bs::funnel(w[k].w, w[k].y, e[k]);
         }
         csa_add<NL, N>(acc[g], lo, hi);
     }
 }
 
+// Asynchronous copy of one LDS stage: channels [c0, c0 + cs) of the block's
+// window, channel cl into row `row0 + cl` (pitch `a.pitch` words).  Each row
+// gets the `stride` words from w_base + (delay[d_lo][c] >> 5) on, cut at the
+// end of the channel's words (what lies beyond only feeds output samples past
+// nout, which are never stored).  The copies go global -> LDS directly (one
+// dword per lane and instruction) and complete asynchronously: the caller
+// waits for them before the barrier that publishes the stage.
+__device__ __forceinline__ void fill_stage(const dd::BeamArgs& a, cptr<int32_t> dlo_row,
+                                           int64_t w_base, int stride, int c0, int cs,
+                                           uint2* __restrict__ lds, int lane, int wave) {
+    for (int cl = wave; cl < cs; cl += kWaves) {
+        const int c = c0 + cl;
+        const int64_t w0 = w_base + (dlo_row[c] >> 5);
+        const int64_t avail = a.nwords - w0;   // > 0: w0 < nsamps / 32 + 1 < nwords
+        const int ndw = 2 * static_cast<int>(avail < stride ? avail : stride);
+        const uint32_t* src =
+            reinterpret_cast<const uint32_t*>(a.words + static_cast<int64_t>(c) * a.nwords + w0);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(lds + static_cast<int64_t>(cl) * a.pitch);
+        for (int i = 0; i < ndw; i += 64) {
+            if (i + lane < ndw)
+                __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void*)(src + i + lane),
+                    (__attribute__((address_space(3))) void*)(dst + i), 4, 0, 0);
+        }
+    }
+}
+
+// One stage: start the copy of the next stage into `nxt` (if any), then add
+// this stage's channels from `cur`.  The two buffers are passed as restrict
+// pointers so the compiler knows the LDS reads do not wait on the copy.
+template <int NL, int NDW, int G>
+__device__ __forceinline__ void run_stage(const dd::BeamArgs& a, uint32_t (&acc)[NDW][G][NL],
+                                          cptr<int32_t> dlo_row, int64_t w_base, int stride,
+                                          int c0, int stage_chans, int d_lo,
+                                          const uint2* __restrict__ cur, uint2* __restrict__ nxt,
+                                          bool more, int lane, int wave) {
+    const int cs = min(stage_chans, a.nchans - c0);
+    if (more)
+        fill_stage(a, dlo_row, w_base, stride, c0 + stage_chans,
+                   min(stage_chans, a.nchans - c0 - stage_chans), nxt, lane, wave);
+#pragma unroll
+    for (int i = 0; i < NDW; ++i) {
+        const int d = d_lo + wave + kWaves * i;
+        if (d < a.ndm) {
+            const cptr<uint32_t> trow = as_const(a.offs) + static_cast<int64_t>(d) * a.nchans;
+            int cl = 0;
+            // 8-channel steps: fewer live registers than 16, more resident waves
+#pragma unroll 1
+            for (; cl + 8 <= cs; cl += 8)
+                accumulate_chunk<NL, G, 8>(acc[i], cur + lane, trow, c0 + cl);
+            if (cl + 4 <= cs) accumulate_chunk<NL, G, 4>(acc[i], cur + lane, trow, c0 + cl);
+        }
+    }
+}
+
 // One work item: DM block `dblk` x time tile `tile` of one beam.
+//
+// The LDS holds two stage buffers of `stage_chans` rows each; stage s lives in
+// buffer s & 1, so channel c sits in row c mod (2 * stage_chans) -- the row
+// the offset table assumes.  While the waves work on stage s, the copy of
+// stage s + 1 into the other buffer is in flight.
 template <int NL, int NDW, int G, bool OUT16>
 __device__ __forceinline__ void process_item(const dd::BeamArgs& a, int tile, int dblk,
                                              int stage_chans, uint2* lds, int lane, int wave) {
@@ -72,12 +167,11 @@ __device__ __forceinline__ void process_item(const dd::BeamArgs& a, int tile, in
     constexpr int T = 2048 * G;
     const int64_t T0 = static_cast<int64_t>(tile) * T;
     const int d_lo = dblk * ND;
-    // words per LDS channel row; T/32 + 1 arrives as a kernel argument so that
-    // the compiler keeps each channel's row offset a single scalar and the
-    // groups' reads fold into the LDS instructions' immediate offsets
-    const int stride = a.tile_words + a.skew[dblk];
+    // words this block needs per channel row (<= a.pitch)
+    const int stride = a.tile_words + as_const(a.skew)[dblk];
     const int64_t w_base = T0 >> 5;
-    const int32_t* dlo_row = a.delays + static_cast<int64_t>(d_lo) * a.nchans;
+    const cptr<int32_t> dlo_row = as_const(a.delays) + static_cast<int64_t>(d_lo) * a.nchans;
+    const int nst = (a.nchans + stage_chans - 1) / stage_chans;
 
     uint32_t acc[NDW][G][NL];
 #pragma unroll
@@ -87,40 +181,19 @@ __device__ __forceinline__ void process_item(const dd::BeamArgs& a, int tile, in
 #pragma unroll
             for (int l = 0; l < NL; ++l) acc[i][g][l] = 0u;
 
+    fill_stage(a, dlo_row, w_base, stride, 0, min(stage_chans, a.nchans), lds, lane, wave);
+    const int64_t half = static_cast<int64_t>(stage_chans) * a.pitch;
 #pragma unroll 1
-    for (int c0 = 0; c0 < a.nchans; c0 += stage_chans) {
-        const int cs = min(stage_chans, a.nchans - c0);
-        // Stage fill: channel cl gets words [w_base + (delay[d_lo][c] >> 5), +stride).
-        for (int cl = wave; cl < cs; cl += kWaves) {
-            const int c = c0 + cl;
-            const int64_t w0 = w_base + (dlo_row[c] >> 5);
-            const uint2* src = a.words + static_cast<int64_t>(c) * a.nwords;
-            uint2* dst = lds + cl * stride;
-            for (int i = lane; i < stride; i += 64) {
-                const int64_t w = w0 + i;
-                dst[i] = w < a.nwords ? src[w] : make_uint2(0u, 0u);
-            }
-        }
+    for (int st = 0; st < nst; ++st) {
+        const int c0 = st * stage_chans;
+        // this wave's copies of stage st are done; after the barrier every
+        // wave's are, and every wave has finished stage st - 1, whose buffer
+        // the copy of stage st + 1 now overwrites
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-
-#pragma unroll
-        for (int i = 0; i < NDW; ++i) {
-            const int d = d_lo + wave + kWaves * i;
-            if (d < a.ndm) {
-                const int32_t* drow = a.delays + static_cast<int64_t>(d) * a.nchans;
-                int cl = 0;
-#pragma unroll 1
-                for (; cl + 16 <= cs; cl += 16)
-                    accumulate_chunk<NL, G, 16>(acc[i], lds, drow, dlo_row, c0 + cl, cl, stride, lane);
-                if (cl + 8 <= cs) {
-                    accumulate_chunk<NL, G, 8>(acc[i], lds, drow, dlo_row, c0 + cl, cl, stride, lane);
-                    cl += 8;
-                }
-                if (cl + 4 <= cs)
-                    accumulate_chunk<NL, G, 4>(acc[i], lds, drow, dlo_row, c0 + cl, cl, stride, lane);
-            }
-        }
-        __syncthreads();
+        run_stage<NL, NDW, G>(a, acc, dlo_row, w_base, stride, c0, stage_chans, d_lo,
+                              (st & 1) ? lds + half : lds, (st & 1) ? lds : lds + half,
+                              st + 1 < nst, lane, wave);
     }
 
     // Write: counters -> integers, one 32-sample group per lane and group.
@@ -210,12 +283,18 @@ __global__ __launch_bounds__(kThreads) void dedisperse_persistent_kernel(
     for (;;) {
         if (threadIdx.x == 0) item_sh = static_cast<long long>(q_lo + atomicAdd(&counters[q], 1ull));
         __syncthreads();
-        const int64_t item = item_sh;
+        // The popped item is uniform over the block: keep it (and all that is
+        // derived from it: beam, delay rows, skew) in scalar registers.
+        const unsigned long long raw = static_cast<unsigned long long>(item_sh);
+        const int64_t item = static_cast<int64_t>(
+            (static_cast<unsigned long long>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(raw >> 32))) << 32) |
+            static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(raw))));
         __syncthreads();
         if (item >= q_hi) break;
+        const cptr<dd::BeamArgs> cb = as_const(beams);
         int b = 0;
-        while (b + 1 < nbeams && item >= beams[b + 1].item_begin) ++b;
-        const dd::BeamArgs& a = beams[b];
+        while (b + 1 < nbeams && item >= cb[b + 1].item_begin) ++b;
+        const dd::BeamArgs a = load_beam(cb + b);
         const int64_t local = item - a.item_begin;
         process_item<NL, NDW, G, OUT16>(a, static_cast<int>(local / a.n_dm_blocks),
                                         static_cast<int>(local % a.n_dm_blocks), stage_chans, lds,
@@ -277,11 +356,14 @@ int occupancy_cfg(size_t lds) {
 namespace dd {
 
 
-size_t tile_lds_bytes(const dedisp_plan_s* p, const TileConfig& cfg) {
+int tile_pitch(const dedisp_plan_s* p, const TileConfig& cfg) {
     const int k = dm_block_index(cfg.dms_per_block);
-    if (k < 0) return 0;
-    return static_cast<size_t>(cfg.stage_chans) * (2048 * cfg.groups / 32 + 1 + p->skew_max[k]) *
-           sizeof(uint2);
+    return k < 0 ? 0 : 2048 * cfg.groups / 32 + 1 + p->skew_max[k];
+}
+
+size_t tile_lds_bytes(const dedisp_plan_s* p, const TileConfig& cfg) {
+    // two stage buffers of stage_chans rows
+    return 2 * static_cast<size_t>(cfg.stage_chans) * tile_pitch(p, cfg) * sizeof(uint2);
 }
 
 BeamArgs beam_args(const dedisp_plan_s* p, const uint2* words, int64_t nwords, int64_t nout,
@@ -294,11 +376,13 @@ BeamArgs beam_args(const dedisp_plan_s* p, const uint2* words, int64_t nwords, i
     a.ndm = p->ndm;
     a.nout = nout;
     a.delays = p->d_delays;
+    a.offs = offset_table(p, cfg, false);
     a.skew = k >= 0 ? p->d_skew[k] : nullptr;
     a.out = out;
     a.n_dm_blocks = (p->ndm + cfg.dms_per_block - 1) / cfg.dms_per_block;
     const int64_t T = 2048 * cfg.groups;
     a.tile_words = static_cast<int>(T / 32 + 1);
+    a.pitch = tile_pitch(p, cfg);
     a.item_begin = 0;
     a.n_items = ((nout + T - 1) / T) * a.n_dm_blocks;
     return a;
@@ -320,6 +404,8 @@ dedisp_status launch_dedisperse(const dedisp_plan_s* p, const uint2* words, int6
                     "DM block of %d trials spans %d words of skew: LDS tile of %zu bytes too large",
                     cfg.dms_per_block, p->skew_max[k], lds);
     const int nl = levels_for(p->nchans);
+    dedisp_status st = DEDISP_OK;
+    if (!offset_table(p, cfg, true, &st)) return st;
     const BeamArgs a = beam_args(p, words, nwords, nout, out, cfg);
     hipError_t e = hipErrorInvalidValue;
 #define DD_DISPATCH(NL_, NDW_, G_)                                                    \

@@ -137,13 +137,104 @@ extern "C" dedisp_status dedisp_plan_create(int32_t nchans, double f_top, double
                     "device setup of the plan failed: %s", hipGetErrorString(e));
     }
     dd::apply_env_cache(p);
+    {
+        dedisp_status st = DEDISP_OK;
+        if (!dd::offset_table(p, dd::default_tile_config(p), true, &st)) {
+            dedisp_plan_destroy(p);
+            return st;
+        }
+    }
     *plan_out = p;
     dd::clear_error();
     return DEDISP_OK;
 }
 
+namespace dd {
+
+const uint32_t* offset_table(const dedisp_plan_s* p, const TileConfig& cfg, bool build,
+                             dedisp_status* st) {
+    if (st) *st = DEDISP_OK;
+    std::lock_guard<std::mutex> lock(p->tab_mu);
+    for (const auto& t : p->tabs)
+        if (t.dms == cfg.dms_per_block && t.groups == cfg.groups && t.stage == cfg.stage_chans)
+            return t.d;
+    if (!build) {
+        if (st) *st = fail(DEDISP_ERR_INVALID_ARG, "no offset table for tile (%d, %d, %d)",
+                           cfg.dms_per_block, cfg.groups, cfg.stage_chans);
+        return nullptr;
+    }
+    const int k = dm_block_index(cfg.dms_per_block);
+    if (k < 0 || cfg.groups < 1 || cfg.stage_chans < 4) {
+        if (st) *st = fail(DEDISP_ERR_INVALID_ARG, "unsupported tile configuration");
+        return nullptr;
+    }
+    const int nc = p->nchans;
+    const int64_t pitch = 64 * cfg.groups + 1 + p->skew_max[k];
+    std::vector<uint32_t> h(static_cast<size_t>(p->ndm) * nc);
+    for (int d = 0; d < p->ndm; ++d) {
+        const int blk = d / cfg.dms_per_block;
+        const int32_t* row = &p->delays[static_cast<size_t>(d) * nc];
+        const int32_t* lo = &p->delays[static_cast<size_t>(blk) * cfg.dms_per_block * nc];
+        for (int c = 0; c < nc; ++c) {
+            const int64_t words = (c % cfg.stage_chans) * pitch + (row[c] >> 5) - (lo[c] >> 5);
+            const int64_t bytes = words * 8;
+            if (words < 0 || (bytes << 5) >= (int64_t(1) << 32)) {
+                if (st) *st = fail(DEDISP_ERR_UNSUPPORTED, "LDS offset out of range");
+                return nullptr;
+            }
+            h[static_cast<size_t>(d) * nc + c] =
+                static_cast<uint32_t>(bytes << 5) | static_cast<uint32_t>(row[c] & 31);
+        }
+    }
+    // upload on a private stream and wait for it, so that a launch on any
+    // stream afterwards sees the whole table
+    uint32_t* dptr = nullptr;
+    hipStream_t up = nullptr;
+    hipError_t e = hipMalloc(&dptr, h.size() * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&up, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dptr, h.data(), h.size() * sizeof(uint32_t), hipMemcpyHostToDevice, up);
+    if (e == hipSuccess) e = hipStreamSynchronize(up);
+    if (up) (void)hipStreamDestroy(up);
+    if (e != hipSuccess) {
+        if (dptr) (void)hipFree(dptr);
+        if (st)
+            *st = fail(e == hipErrorOutOfMemory ? DEDISP_ERR_OUT_OF_MEMORY : DEDISP_ERR_HIP,
+                       "offset table upload failed: %s", hipGetErrorString(e));
+        return nullptr;
+    }
+    p->tabs.push_back({cfg.dms_per_block, cfg.groups, cfg.stage_chans, dptr});
+    return dptr;
+}
+
+void drop_offset_tables(const dedisp_plan_s* p, const std::vector<TileConfig>& keep) {
+    std::lock_guard<std::mutex> lock(p->tab_mu);
+    std::vector<dedisp_plan_s::OffsetTable> kept;
+    for (const auto& t : p->tabs) {
+        bool k = false;
+        for (const TileConfig& c : keep)
+            k = k || (t.dms == c.dms_per_block && t.groups == c.groups && t.stage == c.stage_chans);
+        if (k)
+            kept.push_back(t);
+        else
+            (void)hipFree(t.d);
+    }
+    p->tabs.swap(kept);
+}
+
+std::vector<TileConfig> offset_table_shapes(const dedisp_plan_s* p) {
+    std::lock_guard<std::mutex> lock(p->tab_mu);
+    std::vector<TileConfig> v;
+    for (const auto& t : p->tabs) v.push_back(TileConfig{t.dms, t.groups, t.stage});
+    return v;
+}
+
+}  // namespace dd
+
 extern "C" dedisp_status dedisp_plan_destroy(dedisp_plan p) {
     if (!p) return dd::fail(DEDISP_ERR_INVALID_ARG, "plan is NULL");
+    for (const auto& t : p->tabs) (void)hipFree(t.d);
+    p->tabs.clear();
     if (p->d_delays) (void)hipFree(p->d_delays);
     for (int k = 0; k < dedisp_plan_s::kNumDmBlock; ++k)
         if (p->d_skew[k]) (void)hipFree(p->d_skew[k]);

@@ -195,7 +195,7 @@ __device__ void load_prefix(const T* __restrict__ row, int64_t nout, int64_t fir
     }
     __syncthreads();
     // each thread scans a contiguous chunk (odd chunk stride: no bank conflicts)
-    const int chunk = ((n - 1) + kThreads - 1) / kThreads;
+    const int chunk = (((n - 1) + kThreads - 1) / kThreads) | 1;
     const int lo = 1 + threadIdx.x * chunk;
     const int hi = min(n, lo + chunk);
     uint32_t sum = 0;
@@ -335,10 +335,12 @@ __device__ __forceinline__ void stats_full_nw(uint32_t* pl, const dd::Widths& W,
 #pragma unroll
     for (int wi = 0; wi < NW; ++wi) r[wi * kThreads + t] = s2[wi];
     __syncthreads();
+    // thread (wi, l) sums partials l, l+16, ..., l+240 of width wi: the 16
+    // lanes of one width read 16 consecutive values (no bank conflicts)
     uint64_t acc = 0;
     if (t < NW * 16) {
-        const uint64_t* q = r + (t / 16) * kThreads + (t % 16) * 16;
-        for (int k = 0; k < 16; ++k) acc += q[k];
+        const uint64_t* q = r + (t / 16) * kThreads + (t % 16);
+        for (int k = 0; k < 16; ++k) acc += q[16 * k];
     }
     __syncthreads();
     if (t < NW * 16) r[t] = acc;
@@ -359,11 +361,11 @@ __device__ __forceinline__ void stats_full_nw(uint32_t* pl, const dd::Widths& W,
     uint64_t a1 = 0;
     uint32_t am = 0;
     if (t < NW * 16) {
-        const uint64_t* q = r + (t / 16) * kThreads + (t % 16) * 16;
-        const uint32_t* qm = pl + 2 * NW * kThreads + (t / 16) * kThreads + (t % 16) * 16;
+        const uint64_t* q = r + (t / 16) * kThreads + (t % 16);
+        const uint32_t* qm = pl + 2 * NW * kThreads + (t / 16) * kThreads + (t % 16);
         for (int k = 0; k < 16; ++k) {
-            a1 += q[k];
-            am = max(am, qm[k]);
+            a1 += q[16 * k];
+            am = max(am, qm[16 * k]);
         }
     }
     __syncthreads();

@@ -432,6 +432,13 @@ extern "C" dedisp_status dedisp_serve_create(const dedisp_plan* plans, int32_t n
         delete s;
         return fail(DEDISP_ERR_UNSUPPORTED, "tile shape does not fit (LDS %zu bytes)", s->lds);
     }
+    for (int b = 0; b < nbeams; ++b) {
+        dedisp_status st = DEDISP_OK;
+        if (!dd::offset_table(plans[b], s->cfg, true, &st)) {
+            delete s;
+            return st;
+        }
+    }
     // HBM admission: resident overlaps first, then as many chunk slots as fit.
     const size_t slot_bytes = dedisp_serve_slot_bytes(plans, nbeams, chunk_nsamps, widths, nwidths);
     size_t resident = 0;

@@ -121,7 +121,7 @@ namespace dd {
 TileConfig default_tile_config(const dedisp_plan_s* p) {
     const int packed = p->tuned.load();
     if (packed) return TileConfig{packed >> 16, (packed >> 8) & 0xFF, packed & 0xFF};
-    return TileConfig{16, 2, 32};
+    return TileConfig{16, 1, 16};
 }
 
 TileConfig tuned_or_default(const dedisp_plan_s* p, const char* cache_path, int out_u16) {
@@ -192,10 +192,12 @@ extern "C" dedisp_status dedisp_autotune(dedisp_plan p, int64_t nsamps, dedisp_o
         return fail(e == hipErrorOutOfMemory ? DEDISP_ERR_OUT_OF_MEMORY : DEDISP_ERR_HIP,
                     "autotune setup: %s", hipGetErrorString(e));
     }
+    // tables built for candidate shapes are freed again, all but the winner's
+    std::vector<dd::TileConfig> had = dd::offset_table_shapes(p);
     hipLaunchKernelGGL(fill_random_kernel, dim3(static_cast<unsigned>((in_bytes + 255) / 256)), dim3(256),
                        0, s, in, in_bytes, 0x5EEDull + static_cast<uint64_t>(p->ndm));
     e = dd::launch_repack(in, nsamps, p->nchans, words, nwords, s);
-    const dd::TileConfig base{16, 2, 32};
+    const dd::TileConfig base{16, 1, 16};
     if (e == hipSuccess)
         st = dd::launch_dedisperse(p, words, nwords, nout, ref, u16, base, s);
     if (e != hipSuccess || st != DEDISP_OK) {
@@ -243,6 +245,8 @@ extern "C" dedisp_status dedisp_autotune(dedisp_plan p, int64_t nsamps, dedisp_o
         }
     }
     cleanup();
+    had.push_back(best);
+    dd::drop_offset_tables(p, had);
     if (e != hipSuccess) return fail(DEDISP_ERR_HIP, "autotune: %s", hipGetErrorString(e));
     p->tuned.store((best.dms_per_block << 16) | (best.groups << 8) | best.stage_chans);
     if (best_out) *best_out = dedisp_tile{best.dms_per_block, best.groups, best.stage_chans};
