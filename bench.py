@@ -26,11 +26,18 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Derived ALU peak (integer adds the path needs, at the narrowest native
-# width that holds the exact result, 16 bits): 256 CUs x 64 lanes x 2
-# (v_pk_add_u16) x 2.4 GHz.
-PEAK_PK16_ADDS = 256 * 64 * 2 * 2.4e9
-PEAK_I32_ADDS = 256 * 64 * 2.4e9
+# Derived ALU peak of the bit-sliced dedispersion.  The chip issues
+# 256 CUs x 64 32-bit lane operations per clock at 2.4 GHz (3.93e13/s).  In
+# the bit-sliced form one lane operation handles 32 samples of one bit-plane;
+# adding one channel's 32 two-bit samples to a trial's counters takes at
+# least 6 of them: two funnel shifts (align the lo and hi planes to the
+# delay) and two full adders of two 3-input bit operations each (the carry-
+# save reduction absorbs the two new bits).  Peak = 3.93e13 * 32 / 6 adds/s.
+LANE_OPS = 256 * 64 * 2.4e9
+PEAK_BITSLICE_ADDS = LANE_OPS * 32 / 6
+# LDS: each (trial, channel, 32 samples) reads 16 bytes per lane; at 128
+# bytes per clock per CU that bounds the adds at 256 * 2.4e9 * 128 / 16 * 32.
+PEAK_LDS_ADDS = 256 * 2.4e9 * 128 / 16 * 32
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dedisperse_survey_traffic.json")
 KERNEL_SOURCES = ["dedisperse.hip", "bitslice.hpp", "csa_tree.inc", "repack.hip"]
 
@@ -169,10 +176,10 @@ def main():
     adds = ndm * nout * fb.nchans
     achieved = adds / (ded_ms * 1e-3)
     traffic = traffic_per_launch()
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_PK16_ADDS / 1e12,
-                "unit": "Tadd/s", "frac": achieved / PEAK_PK16_ADDS, "traffic": traffic,
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_BITSLICE_ADDS / 1e12,
+                "unit": "Tadd/s", "frac": achieved / PEAK_BITSLICE_ADDS, "traffic": traffic,
                 "kernel": "dedisperse_kernel", "kernel_ms": ded_ms,
-                "frac_of_i32_peak": achieved / PEAK_I32_ADDS}
+                "lds_peak": PEAK_LDS_ADDS / 1e12, "lds_frac": achieved / PEAK_LDS_ADDS}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -14,11 +14,13 @@
 // cut iff B >= B_thr = ceil((S1 + isqrt(floor(k^2 D)) + 1) / n), k being the
 // exact binary value of the float threshold (128/256-bit integer helpers).
 //
-// Events (maximal runs of above-cut samples of one series, section 2.3's
-// "contiguous regions gathered into individual events") are compacted
-// deterministically: count run starts per (width, DM, segment), exclusive
-// scan, then write each event at its offset -- the output order is (width,
-// DM, t_start) without any sort.
+// Events (section 2.3: each maximal run of above-cut samples of one series
+// is one event) are compacted deterministically: count run starts per
+// (width, DM, segment), exclusive scan, then write each event at its offset
+// -- the output order is (width, DM, t_start) without any sort.  Only the
+// (DM, segment)s whose largest boxcar reaches the cut are counted, and only
+// those with events are written: both passes work through lists of them.
+#include <algorithm>
 #include <cmath>
 
 #include "dedisp_internal.hpp"
@@ -177,16 +179,29 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* w
 
 // Fill pl[0..n) with the running sum of the series values s[first + i]
 // (values outside [0, nout) count as 0): pl[i] = sum_{k<i} s[first+k].
+// Loads and LDS reads are issued in batches of kBatch per thread so that
+// their latencies overlap.
+constexpr int kBatch = 12;
+
 template <typename T>
 __device__ void load_prefix(const T* __restrict__ row, int64_t nout, int64_t first, int n,
                             uint32_t* pl, uint32_t* wave_tot, uint32_t* vmax = nullptr) {
     // coalesced load of the raw values into pl[1..n)
     uint32_t m = 0;
-    for (int i = threadIdx.x; i < n - 1; i += kThreads) {
-        const int64_t t = first + i;
-        const uint32_t v = (t >= 0 && t < nout) ? static_cast<uint32_t>(row[t]) : 0u;
-        pl[i + 1] = v;
-        m = max(m, v);
+    for (int base = threadIdx.x; base < n - 1; base += kBatch * kThreads) {
+        uint32_t v[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const int i = base + k * kThreads;
+            const int64_t t = first + i;
+            v[k] = (i < n - 1 && t >= 0 && t < nout) ? static_cast<uint32_t>(row[t]) : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const int i = base + k * kThreads;
+            if (i < n - 1) pl[i + 1] = v[k];
+            m = max(m, v[k]);
+        }
     }
     if (vmax) {
 #pragma unroll
@@ -199,12 +214,24 @@ __device__ void load_prefix(const T* __restrict__ row, int64_t nout, int64_t fir
     const int lo = 1 + threadIdx.x * chunk;
     const int hi = min(n, lo + chunk);
     uint32_t sum = 0;
-    for (int i = lo; i < hi; ++i) sum += pl[i];
+    for (int i0 = lo; i0 < hi; i0 += kBatch) {
+        uint32_t v[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) v[k] = i0 + k < hi ? pl[i0 + k] : 0u;
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) sum += v[k];
+    }
     const uint32_t base = block_exclusive_scan(sum, wave_tot);
     uint32_t run = base;
-    for (int i = lo; i < hi; ++i) {
-        run += pl[i];
-        pl[i] = run;
+    for (int i0 = lo; i0 < hi; i0 += kBatch) {
+        uint32_t v[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) v[k] = i0 + k < hi ? pl[i0 + k] : 0u;
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            run += v[k];
+            if (i0 + k < hi) pl[i0 + k] = run;
+        }
     }
     if (threadIdx.x == 0) pl[0] = 0u;
     __syncthreads();
@@ -306,8 +333,8 @@ __device__ __forceinline__ void width_sums_full(const uint32_t* pl, const uint32
 template <int NW>
 __device__ __forceinline__ void stats_full_nw(uint32_t* pl, const dd::Widths& W, uint64_t* s1_out,
                                               u128* s2_out, uint32_t* mx_out) {
-    uint32_t s1[NW], mx[NW];
-    uint64_t s2[NW];
+    uint64_t s1[NW], s2[NW];
+    uint32_t mx[NW];
     int woff[NW];
 #pragma unroll
     for (int wi = 0; wi < NW; ++wi) {
@@ -316,6 +343,16 @@ __device__ __forceinline__ void stats_full_nw(uint32_t* pl, const dd::Widths& W,
         s2[wi] = 0;
         woff[wi] = W.w[wi];
     }
+    // Sum of the segment's boxcars by telescoping: with P the running sums,
+    //   sum_{j<L} (P[j+1+w] - P[j+1]) = sum_{k=1..w} (P[L+k] - P[k]),
+    // each term a sum of L samples (below 2^32 by the caller's check).
+    constexpr int L = kPerThread * kThreads;
+    for (int k = threadIdx.x + 1; k <= woff[NW - 1]; k += kThreads) {
+        const uint64_t dk = pl[L + k] - pl[k];
+#pragma unroll
+        for (int wi = 0; wi < NW; ++wi)
+            if (k <= woff[wi]) s1[wi] += dk;
+    }
     const uint32_t* base = pl + 1 + threadIdx.x;
 #pragma unroll 4
     for (int j = 0; j < kPerThread; ++j) {
@@ -323,7 +360,6 @@ __device__ __forceinline__ void stats_full_nw(uint32_t* pl, const dd::Widths& W,
 #pragma unroll
         for (int wi = 0; wi < NW; ++wi) {
             const uint32_t b = base[j * kThreads + woff[wi]] - p0;
-            s1[wi] += b;
             s2[wi] += static_cast<uint64_t>(b) * b;
             mx[wi] = max(mx[wi], b);
         }
@@ -407,7 +443,10 @@ __global__ __launch_bounds__(kThreads) void boxcar_stats_kernel(const T* __restr
     const int npos = static_cast<int>(min<int64_t>(L, nbx - s0));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool small = static_cast<uint64_t>(vmax) * static_cast<uint64_t>(w_max) < (uint64_t(1) << 26);
-    const bool full = small && npos == kPerThread * kThreads;
+    // full fast path: a whole segment, squares summable in 64 bits, and every
+    // sum of L consecutive samples below 2^32 (for the telescoped S1)
+    const bool full = small && npos == kPerThread * kThreads && vmax < (1u << 19) &&
+                      L == kPerThread * kThreads;
     constexpr int NWS = NW > 0 ? NW : 1;
     if (NW > 0 && full) {
         __shared__ uint64_t f1[NWS];
@@ -463,6 +502,10 @@ __global__ __launch_bounds__(kThreads) void series_threshold_kernel(int nseries,
                                                                     int64_t nbx, uint32_t kmant,
                                                                     int kexp2, dd::PeaksWs ws) {
     const int s = blockIdx.x * kThreads + threadIdx.x;
+    if (s == 0) {
+        ws.nlist[0] = 0u;   // the mark and count passes append to the work lists
+        ws.nlist[1] = 0u;
+    }
     if (s >= nseries) return;
     uint64_t s1 = 0;
     u128 s2 = 0;
@@ -501,52 +544,75 @@ __global__ __launch_bounds__(kThreads) void series_threshold_kernel(int nseries,
     ws.sqrt_d[s] = sqrt(u128_to_double(d));
 }
 
-// Pass 3: number of run starts per (width, DM, segment).
+// Pass 3a: one thread per (DM, segment).  A segment where, for some width,
+// the largest boxcar reaches the series' cut goes on the count work list;
+// every other segment gets zero run starts for all widths here.
+__global__ __launch_bounds__(kThreads) void mark_kernel(int ndm, int nseg, int nw, dd::PeaksWs ws) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (idx >= static_cast<int64_t>(ndm) * nseg) return;
+    const int d = static_cast<int>(idx / nseg);
+    bool any = false;
+    for (int wi = 0; wi < nw; ++wi)
+        any |= ws.part_max[static_cast<int64_t>(wi) * ndm * nseg + idx] >= ws.thr32[wi * ndm + d];
+    if (any) {
+        ws.list[atomicAdd(&ws.nlist[0], 1u)] = static_cast<uint32_t>(idx);
+    } else {
+        for (int wi = 0; wi < nw; ++wi) ws.counts[static_cast<int64_t>(wi) * ndm * nseg + idx] = 0;
+    }
+}
+
+// Pass 3b: number of run starts per (width, DM, segment) of the listed
+// segments (a fixed grid of blocks works through the list).  Segments with
+// any start go on the write list.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void peaks_count_kernel(const T* __restrict__ in,
+__global__ __launch_bounds__(kThreads) void peaks_count_kernel(const T* __restrict__ in, int ndm,
                                                                int64_t nout, int64_t nbx,
                                                                dd::Widths W, int L, int nseg,
                                                                dd::PeaksWs ws) {
     extern __shared__ uint32_t pl[];
     __shared__ uint32_t wave_tot[kThreads / 64];
     __shared__ uint32_t cnt[dd::kMaxWidths];
-    const int d = blockIdx.y;
-    const int seg = blockIdx.x;
-    const int ndm = gridDim.y;
-    // Skip the scan when no width of this (DM, segment) reaches its cut.
-    bool any = false;
-    for (int wi = 0; wi < W.n; ++wi) {
-        const int64_t idx = (static_cast<int64_t>(wi) * ndm + d) * nseg + seg;
-        any |= ws.part_max[idx] >= ws.thr32[wi * ndm + d];
-    }
-    if (!any) {
-        if (threadIdx.x < W.n)
-            ws.counts[(static_cast<int64_t>(threadIdx.x) * ndm + d) * nseg + seg] = 0;
-        return;
-    }
-    const int64_t s0 = static_cast<int64_t>(seg) * L;
-    const int n = L + W.w[W.n - 1] + 1;
-    if (threadIdx.x < dd::kMaxWidths) cnt[threadIdx.x] = 0;
-    load_prefix(in + static_cast<int64_t>(d) * nout, nout, s0 - 1, n, pl, wave_tot);
-    const int npos = static_cast<int>(min<int64_t>(L, nbx - s0));
+    const uint32_t nitems = ws.nlist[0];
     const int lane = threadIdx.x & 63;
-    for (int wi = 0; wi < W.n; ++wi) {
-        const uint32_t thr = ws.thr32[wi * ndm + d];
-        if (ws.part_max[(static_cast<int64_t>(wi) * ndm + d) * nseg + seg] < thr) continue;
-        const int w = W.w[wi];
-        uint32_t c = 0;
-        for (int i = threadIdx.x; i < npos; i += kThreads) {
-            const bool above = pl[i + 1 + w] - pl[i + 1] >= thr;
-            const bool prev = (s0 + i > 0) && (pl[i + w] - pl[i] >= thr);
-            c += (above && !prev) ? 1u : 0u;
-        }
+    for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int64_t idx = ws.list[item];
+        const int d = static_cast<int>(idx / nseg);
+        const int seg = static_cast<int>(idx % nseg);
+        const int64_t s0 = static_cast<int64_t>(seg) * L;
+        const int n = L + W.w[W.n - 1] + 1;
+        if (threadIdx.x < dd::kMaxWidths) cnt[threadIdx.x] = 0;
+        load_prefix(in + static_cast<int64_t>(d) * nout, nout, s0 - 1, n, pl, wave_tot);
+        const int npos = static_cast<int>(min<int64_t>(L, nbx - s0));
+        for (int wi = 0; wi < W.n; ++wi) {
+            const uint32_t thr = ws.thr32[wi * ndm + d];
+            if (ws.part_max[(static_cast<int64_t>(wi) * ndm + d) * nseg + seg] < thr) continue;
+            const int w = W.w[wi];
+            uint32_t c = 0;
+            for (int i0 = threadIdx.x; i0 < npos; i0 += 4 * kThreads) {
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
-        if (lane == 0 && c) atomicAdd(&cnt[wi], c);
+                for (int k = 0; k < 4; ++k) {
+                    const int i = i0 + k * kThreads;
+                    if (i < npos) {
+                        const bool above = pl[i + 1 + w] - pl[i + 1] >= thr;
+                        const bool prev = (s0 + i > 0) && (pl[i + w] - pl[i] >= thr);
+                        c += (above && !prev) ? 1u : 0u;
+                    }
+                }
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+            if (lane == 0 && c) atomicAdd(&cnt[wi], c);
+        }
+        __syncthreads();
+        if (threadIdx.x < W.n)
+            ws.counts[(static_cast<int64_t>(threadIdx.x) * ndm + d) * nseg + seg] = cnt[threadIdx.x];
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+            for (int wi = 0; wi < W.n; ++wi) tot += cnt[wi];
+            if (tot) ws.list2[atomicAdd(&ws.nlist[1], 1u)] = static_cast<uint32_t>(idx);
+        }
+        __syncthreads();   // pl and cnt are reused by the next item
     }
-    __syncthreads();
-    if (threadIdx.x < W.n)
-        ws.counts[(static_cast<int64_t>(threadIdx.x) * ndm + d) * nseg + seg] = cnt[threadIdx.x];
 }
 
 // Exclusive scan of counts (uint32) into offsets (int64): three small kernels.
@@ -591,24 +657,72 @@ __global__ __launch_bounds__(kThreads) void scan_add_kernel(int64_t* __restrict_
     if (i < n) offs[i] += chunk_tot[i / kScanChunk];
 }
 
-// Walk the run that starts at t with boxcar value b (sliding window sum) and
-// write its event record.
+// Walk the run that starts at t with boxcar value b and write its event
+// record.  Positions whose boxcar the block's running sums cover (local index
+// below `lim`, running sums pl relative to s0) are read from LDS, kWalk at a
+// time (the reads do not depend on each other); a run that goes on past them
+// continues on the series in global memory with the sliding-window update,
+// again loading kWalk positions' samples at once.
+constexpr int kWalk = 16;
+
 template <typename T>
 __device__ __forceinline__ void write_event(const T* __restrict__ row, int64_t nbx, int w, int wi, int d,
                                             int64_t t, uint32_t b, uint32_t thr, uint64_t s1, double sqrt_d,
-                                            dedisp_event* __restrict__ out) {
-    int64_t te = t, tp = t, u = t;
+                                            dedisp_event* __restrict__ out, const uint32_t* pl,
+                                            int64_t s0, int lim) {
+    int64_t te = t, tp = t;
     uint32_t cur = b, best = b;
-    while (u + 1 < nbx) {
-        const uint32_t nb = cur + static_cast<uint32_t>(row[u + w]) - static_cast<uint32_t>(row[u]);
-        if (nb < thr) break;
-        ++u;
-        cur = nb;
-        te = u;
-        if (nb > best) {
-            best = nb;
-            tp = u;
+    bool open = true;                       // the run has not ended yet
+    int64_t u = t;                          // last position of the run so far
+    while (open && u + 1 < nbx && u + 1 - s0 < lim) {
+        uint32_t bb[kWalk];
+#pragma unroll
+        for (int k = 0; k < kWalk; ++k) {
+            const int64_t j = u + 1 + k - s0;
+            bb[k] = (j < lim && u + 1 + k < nbx) ? pl[j + 1 + w] - pl[j + 1] : 0u;
         }
+        int k = 0;
+        for (; k < kWalk; ++k) {
+            const int64_t v = u + 1 + k;
+            if (v >= nbx || v - s0 >= lim) break;   // leave the LDS window: continue below
+            if (bb[k] < thr) {
+                open = false;
+                break;
+            }
+            cur = bb[k];
+            te = v;
+            if (cur > best) {
+                best = cur;
+                tp = v;
+            }
+        }
+        u += k;
+    }
+    while (open && u + 1 < nbx) {
+        uint32_t add[kWalk], sub[kWalk];
+#pragma unroll
+        for (int k = 0; k < kWalk; ++k) {
+            const bool in = u + 1 + k < nbx;    // then u + k + w <= nout - 1
+            add[k] = in ? static_cast<uint32_t>(row[u + k + w]) : 0u;
+            sub[k] = in ? static_cast<uint32_t>(row[u + k]) : 0u;
+        }
+        int k = 0;
+        for (; k < kWalk; ++k) {
+            if (u + 1 + k >= nbx) break;
+            const uint32_t nb = cur + add[k] - sub[k];
+            if (nb < thr) {
+                open = false;
+                break;
+            }
+            cur = nb;
+            te = u + 1 + k;
+            if (nb > best) {
+                best = nb;
+                tp = te;
+            }
+        }
+        u += k;
+        if (k < kWalk) break;
     }
     const int64_t lval = static_cast<int64_t>(nbx) * best - static_cast<int64_t>(s1);
     dedisp_event ev;
@@ -628,30 +742,77 @@ __device__ __forceinline__ void write_event(const T* __restrict__ row, int64_t n
 // segments with very many starts use block-wide scans in position order.
 constexpr int kMaxStarts = 1024;
 
+// The events of one listed (DM, segment).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void peaks_write_kernel(const T* __restrict__ in,
-                                                               int64_t nout, int64_t nbx,
-                                                               dd::Widths W, int L, int nseg,
-                                                               dd::PeaksWs ws,
-                                                               dedisp_event* __restrict__ events,
-                                                               int64_t capacity) {
-    extern __shared__ uint32_t pl[];
-    __shared__ uint32_t wave_tot[kThreads / 64];
-    __shared__ int starts[kMaxStarts];
-    __shared__ int nstart;
-    __shared__ uint32_t slab_total;
-    const int d = blockIdx.y;
-    const int seg = blockIdx.x;
-    const int ndm = gridDim.y;
-    bool any = false;
-    for (int wi = 0; wi < W.n; ++wi)
-        any |= ws.counts[(static_cast<int64_t>(wi) * ndm + d) * nseg + seg] != 0;
-    if (!any) return;
+__device__ __forceinline__ void write_segment(const T* __restrict__ in, int ndm, int64_t nout, int64_t nbx,
+                              const dd::Widths& W, int L, int nseg, const dd::PeaksWs& ws,
+                              dedisp_event* __restrict__ events, int64_t capacity, int d, int seg,
+                              uint32_t* pl, uint32_t* wave_tot, int* starts, int* nstart_p,
+                              uint32_t* slab_total_p) {
+    int& nstart = *nstart_p;
+    uint32_t& slab_total = *slab_total_p;
     const int64_t s0 = static_cast<int64_t>(seg) * L;
     const int n = L + W.w[W.n - 1] + 1;
     const T* row = in + static_cast<int64_t>(d) * nout;
     load_prefix(row, nout, s0 - 1, n, pl, wave_tot);
     const int npos = static_cast<int>(min<int64_t>(L, nbx - s0));
+
+    // Every width at once when all the segment's run starts fit the list:
+    // width wi's starts fill starts[base[wi] .. base[wi] + count[wi]) (the
+    // counts are known from the count pass), one pass over the positions
+    // finds them, and then all runs of all widths are walked concurrently.
+    __shared__ uint32_t wb[dd::kMaxWidths + 1], wc[dd::kMaxWidths], wfill[dd::kMaxWidths];
+    __shared__ uint32_t wthr[dd::kMaxWidths];
+    if (threadIdx.x < W.n) {
+        const int wi = threadIdx.x;
+        wc[wi] = ws.counts[(static_cast<int64_t>(wi) * ndm + d) * nseg + seg];
+        wthr[wi] = ws.thr32[wi * ndm + d];
+        wfill[wi] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t b = 0;
+        for (int wi = 0; wi < W.n; ++wi) {
+            wb[wi] = b;
+            b += wc[wi];
+        }
+        wb[W.n] = b;
+    }
+    __syncthreads();
+    const uint32_t total = wb[W.n];
+    if (total <= static_cast<uint32_t>(kMaxStarts)) {
+        for (int i = threadIdx.x; i < npos; i += kThreads) {
+            const uint32_t p1 = pl[i + 1], p0 = pl[i];
+            for (int wi = 0; wi < W.n; ++wi) {
+                if (wc[wi] == 0) continue;
+                const int w = W.w[wi];
+                const uint32_t thr = wthr[wi];
+                const bool above = pl[i + 1 + w] - p1 >= thr;
+                const bool prev = (s0 + i > 0) && (pl[i + w] - p0 >= thr);
+                if (above && !prev) {
+                    const uint32_t k = atomicAdd(&wfill[wi], 1u);
+                    if (k < wc[wi]) starts[wb[wi] + k] = i;
+                }
+            }
+        }
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < total; k += kThreads) {
+            int wi = 0;
+            while (wb[wi + 1] <= k) ++wi;
+            const int i = starts[k];
+            uint32_t rank = 0;
+            for (uint32_t q = wb[wi]; q < wb[wi + 1]; ++q) rank += starts[q] < i;
+            const int64_t cidx = (static_cast<int64_t>(wi) * ndm + d) * nseg + seg;
+            const int64_t e = ws.offs[cidx] + rank;
+            const int w = W.w[wi];
+            const int sidx = wi * ndm + d;
+            if (e < capacity)
+                write_event(row, nbx, w, wi, d, s0 + i, pl[i + 1 + w] - pl[i + 1], wthr[wi], ws.s1[sidx],
+                            ws.sqrt_d[sidx], &events[e], pl, s0, n - 1 - w);
+        }
+        return;
+    }
+
     for (int wi = 0; wi < W.n; ++wi) {
         const int64_t cidx = (static_cast<int64_t>(wi) * ndm + d) * nseg + seg;
         const uint32_t cnt = ws.counts[cidx];
@@ -662,6 +823,7 @@ __global__ __launch_bounds__(kThreads) void peaks_write_kernel(const T* __restri
         const int64_t off = ws.offs[cidx];
         const uint64_t s1 = ws.s1[sidx];
         const double sq = ws.sqrt_d[sidx];
+        const int lim = n - 1 - w;   // local positions whose boxcar the running sums cover
         if (cnt <= kMaxStarts) {
             if (threadIdx.x == 0) nstart = 0;
             __syncthreads();
@@ -681,7 +843,8 @@ __global__ __launch_bounds__(kThreads) void peaks_write_kernel(const T* __restri
                 for (int q = 0; q < m; ++q) rank += starts[q] < i;
                 const int64_t e = off + rank;
                 if (e < capacity)
-                    write_event(row, nbx, w, wi, d, s0 + i, pl[i + 1 + w] - pl[i + 1], thr, s1, sq, &events[e]);
+                    write_event(row, nbx, w, wi, d, s0 + i, pl[i + 1 + w] - pl[i + 1], thr, s1, sq, &events[e],
+                                pl, s0, lim);
             }
             __syncthreads();
         } else {
@@ -697,13 +860,36 @@ __global__ __launch_bounds__(kThreads) void peaks_write_kernel(const T* __restri
                 }
                 const uint32_t ex = block_exclusive_scan(start ? 1u : 0u, wave_tot);
                 if (start && rank + ex < capacity)
-                    write_event(row, nbx, w, wi, d, s0 + i, b, thr, s1, sq, &events[rank + ex]);
+                    write_event(row, nbx, w, wi, d, s0 + i, b, thr, s1, sq, &events[rank + ex], pl, s0,
+                                lim);
                 if (threadIdx.x == kThreads - 1) slab_total = ex + (start ? 1u : 0u);
                 __syncthreads();
                 rank += slab_total;
                 __syncthreads();
             }
         }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void peaks_write_kernel(const T* __restrict__ in, int ndm,
+                                                               int64_t nout, int64_t nbx,
+                                                               dd::Widths W, int L, int nseg,
+                                                               dd::PeaksWs ws,
+                                                               dedisp_event* __restrict__ events,
+                                                               int64_t capacity) {
+    extern __shared__ uint32_t pl[];
+    __shared__ uint32_t wave_tot[kThreads / 64];
+    __shared__ int starts[kMaxStarts];
+    __shared__ int nstart;
+    __shared__ uint32_t slab_total;
+    const uint32_t nitems = ws.nlist[1];
+    for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int64_t idx = ws.list2[item];
+        write_segment(in, ndm, nout, nbx, W, L, nseg, ws, events, capacity,
+                      static_cast<int>(idx / nseg), static_cast<int>(idx % nseg), pl, wave_tot,
+                      starts, &nstart, &slab_total);
+        __syncthreads();   // LDS is reused by the next item
     }
 }
 
@@ -717,6 +903,9 @@ int segment_length(int w_max) {
     while (L > 256 && static_cast<int64_t>(L + w_max + 1) * 4 > 60 * 1024) L >>= 1;
     return L;
 }
+
+// Blocks of the list-driven count and write passes (a few per CU).
+constexpr int64_t kListBlocks = 2048;
 
 size_t peaks_lds_bytes(int L, int w_max) { return static_cast<size_t>(L + w_max + 1) * 4; }
 
@@ -809,6 +998,9 @@ PeaksLayout peaks_layout(int ndm, int64_t nout, const Widths& W) {
     lay.o_offs = take(lay.ncounts * 8);
     lay.o_chunk = take(static_cast<size_t>(lay.nchunks) * 8);
     lay.o_total = take(8);
+    lay.o_list = take(static_cast<size_t>(ndm) * lay.nseg * 4);
+    lay.o_list2 = take(static_cast<size_t>(ndm) * lay.nseg * 4);
+    lay.o_nlist = take(8);
     lay.bytes = off;
     return lay;
 }
@@ -830,6 +1022,9 @@ PeaksWs peaks_ws(void* base, const PeaksLayout& lay) {
     ws.offs = reinterpret_cast<int64_t*>(b + lay.o_offs);
     ws.chunk_tot = reinterpret_cast<int64_t*>(b + lay.o_chunk);
     ws.total = reinterpret_cast<int64_t*>(b + lay.o_total);
+    ws.list = reinterpret_cast<uint32_t*>(b + lay.o_list);
+    ws.list2 = reinterpret_cast<uint32_t*>(b + lay.o_list2);
+    ws.nlist = reinterpret_cast<uint32_t*>(b + lay.o_nlist);
     return ws;
 }
 
@@ -846,14 +1041,20 @@ hipError_t launch_peaks_count(const void* in, int in_u16, int ndm, int64_t nout,
                        0, s, nser, lay.nseg, lay.nbx, kmant, kexp2, ws);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    const int64_t nblk = static_cast<int64_t>(ndm) * lay.nseg;
+    hipLaunchKernelGGL(mark_kernel, dim3(static_cast<unsigned>((nblk + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, ndm, lay.nseg, W.n, ws);
+    const dim3 wgrid(static_cast<unsigned>(std::min<int64_t>(nblk, kListBlocks)));
     if (in_u16) {
         set_lds_limit(reinterpret_cast<const void*>(peaks_count_kernel<uint16_t>), lds);
-        hipLaunchKernelGGL(peaks_count_kernel<uint16_t>, grid, dim3(kThreads), lds, s,
-                           static_cast<const uint16_t*>(in), nout, lay.nbx, W, lay.L, lay.nseg, ws);
+        hipLaunchKernelGGL(peaks_count_kernel<uint16_t>, wgrid, dim3(kThreads), lds, s,
+                           static_cast<const uint16_t*>(in), ndm, nout, lay.nbx, W, lay.L, lay.nseg,
+                           ws);
     } else {
         set_lds_limit(reinterpret_cast<const void*>(peaks_count_kernel<int32_t>), lds);
-        hipLaunchKernelGGL(peaks_count_kernel<int32_t>, grid, dim3(kThreads), lds, s,
-                           static_cast<const int32_t*>(in), nout, lay.nbx, W, lay.L, lay.nseg, ws);
+        hipLaunchKernelGGL(peaks_count_kernel<int32_t>, wgrid, dim3(kThreads), lds, s,
+                           static_cast<const int32_t*>(in), ndm, nout, lay.nbx, W, lay.L, lay.nseg,
+                           ws);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -870,17 +1071,18 @@ hipError_t launch_peaks_write(const void* in, int in_u16, int ndm, int64_t nout,
                               int64_t capacity, hipStream_t s) {
     const int w_max = W.w[W.n - 1];
     const size_t lds = peaks_lds_bytes(lay.L, w_max);
-    const dim3 grid(static_cast<unsigned>(lay.nseg), static_cast<unsigned>(ndm));
+    const dim3 grid(static_cast<unsigned>(
+        std::min<int64_t>(static_cast<int64_t>(ndm) * lay.nseg, kListBlocks)));
     if (in_u16) {
         set_lds_limit(reinterpret_cast<const void*>(peaks_write_kernel<uint16_t>), lds);
         hipLaunchKernelGGL(peaks_write_kernel<uint16_t>, grid, dim3(kThreads), lds, s,
-                           static_cast<const uint16_t*>(in), nout, lay.nbx, W, lay.L, lay.nseg, ws,
-                           events, capacity);
+                           static_cast<const uint16_t*>(in), ndm, nout, lay.nbx, W, lay.L, lay.nseg,
+                           ws, events, capacity);
     } else {
         set_lds_limit(reinterpret_cast<const void*>(peaks_write_kernel<int32_t>), lds);
         hipLaunchKernelGGL(peaks_write_kernel<int32_t>, grid, dim3(kThreads), lds, s,
-                           static_cast<const int32_t*>(in), nout, lay.nbx, W, lay.L, lay.nseg, ws,
-                           events, capacity);
+                           static_cast<const int32_t*>(in), ndm, nout, lay.nbx, W, lay.L, lay.nseg,
+                           ws, events, capacity);
     }
     return hipGetLastError();
 }

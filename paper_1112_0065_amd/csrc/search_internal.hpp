@@ -35,6 +35,9 @@ struct PeaksWs {
     int64_t* offs;         // [nw][ndm][nseg] exclusive scan of counts
     int64_t* chunk_tot;    // scan scratch
     int64_t* total;        // total number of events
+    uint32_t* list;        // [ndm * nseg] (DM, segment)s to count (d * nseg + seg)
+    uint32_t* list2;       // [ndm * nseg] (DM, segment)s with events
+    uint32_t* nlist;       // [2] lengths of list and list2
 };
 
 struct PeaksLayout {
@@ -45,7 +48,7 @@ struct PeaksLayout {
     int64_t ncounts;
     int nchunks;
     size_t o_part_s1, o_part_s2lo, o_part_s2hi, o_part_max, o_s1, o_s2lo, o_s2hi, o_thr, o_thr32, o_sqrt_d,
-        o_counts, o_offs, o_chunk, o_total;
+        o_counts, o_offs, o_chunk, o_total, o_list, o_list2, o_nlist;
     size_t bytes;
 };
 
