@@ -29,6 +29,9 @@ from . import _lib as L
 WIDTHS = [1 << i for i in range(10)]
 SNR = 6.0
 NSAMPS = 1 << 17
+# beam seeds: training from TRAIN_SEED on; validation 600.., test 700..;
+# 800.. is left for independent evaluations
+TRAIN_SEED = 10000
 
 
 def nms(events: np.ndarray, ndm: int) -> np.ndarray:
@@ -39,13 +42,15 @@ def nms(events: np.ndarray, ndm: int) -> np.ndarray:
         idx = np.nonzero(events["width_idx"] == wi)[0]
         w = WIDTHS[int(wi)]
         order = idx[np.lexsort((events["t_peak"][idx], events["dm_idx"][idx], -events["snr"][idx]))]
-        acc_d, acc_t = [], []
+        kd = np.empty(len(order), np.int64)
+        kt = np.empty(len(order), np.int64)
+        nk = 0
         for i in order:
             d, t = int(events["dm_idx"][i]), int(events["t_peak"][i])
-            if any(abs(d - ad) < 32 and abs(t - at) < 128 * w for ad, at in zip(acc_d, acc_t)):
+            if nk and np.any((np.abs(kd[:nk] - d) < 32) & (np.abs(kt[:nk] - t) < 128 * w)):
                 continue
-            acc_d.append(d)
-            acc_t.append(t)
+            kd[nk], kt[nk] = d, t
+            nk += 1
             keep.append(int(i))
     return np.array(sorted(keep), dtype=np.int64)
 
@@ -70,6 +75,16 @@ def label(events: np.ndarray, fb, sweep_trial: np.ndarray):
                 match[i] = j
                 break
     return lab, match
+
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "triage_weights.bin")
+
+
+def load_default():
+    """The committed trained network and its score cut: (model, tau, report)."""
+    with open(os.path.splitext(WEIGHTS)[0] + ".json") as f:
+        report = json.load(f)
+    return L.triage_create(WEIGHTS), float(report["tau"]), report
 
 
 def _gen(seed):
@@ -181,10 +196,10 @@ def train(model, tiles, labels, epochs, batch=256, lr=1e-3, seed=0, log=print):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
-    ap.add_argument("--train", type=int, default=96)
-    ap.add_argument("--val", type=int, default=24)
-    ap.add_argument("--test", type=int, default=32)
-    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--train", type=int, default=640)
+    ap.add_argument("--val", type=int, default=80)
+    ap.add_argument("--test", type=int, default=80)
+    ap.add_argument("--epochs", type=int, default=15)
     ap.add_argument("--lr", type=float, default=1e-3)
     args = ap.parse_args()
 
@@ -193,7 +208,7 @@ def main():
 
     os.makedirs(args.out, exist_ok=True)
     t0 = time.time()
-    tr = build(range(500, 500 + args.train), log=log)
+    tr = build(range(TRAIN_SEED, TRAIN_SEED + args.train), log=log)
     va = build(range(600, 600 + args.val), log=log)
     te = build(range(700, 700 + args.test), log=log)
     log(f"datasets built in {time.time() - t0:.1f} s: train {len(tr[1])} ({int(tr[1].sum())} pos), "
@@ -210,7 +225,7 @@ def main():
     report = dict(train_candidates=len(tr[1]), train_positives=int(tr[1].sum()), epochs=args.epochs,
                   lr=args.lr, batch=256, losses=losses, train_seconds=t_train, tau=tau,
                   val=res_val, test=res_test, nsamps=NSAMPS, widths=WIDTHS, snr_thresh=SNR,
-                  seeds=dict(train=[500, 500 + args.train], val=[600, 600 + args.val],
+                  seeds=dict(train=[TRAIN_SEED, TRAIN_SEED + args.train], val=[600, 600 + args.val],
                              test=[700, 700 + args.test]))
     with open(os.path.join(args.out, "triage.json"), "w") as f:
         json.dump(report, f, indent=1)

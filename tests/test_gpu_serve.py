@@ -150,3 +150,53 @@ def test_gap_order_budget_and_backpressure():
     assert st["max_batch"] == 1 and st["chunks_done"] == admitted
     log("one-slot stats", st, "busy retries", busy)
     srv.close()
+
+
+def test_serve_scores_with_trained_model():
+    """With the trained network attached, every event of a chunk gets the
+    score the standalone path (dedisperse -> find_peaks -> tiles -> forward)
+    gives the same window, bit for bit, and the FALLBACK flag stays clear;
+    without a network the flag is set and the events are unchanged."""
+    from paper_1112_0065_amd import _lib as L
+    from paper_1112_0065_amd import triage_train as T
+    torch = torch_dev()
+    model, _, _ = T.load_default()
+    fb = _stream(905, 3, 120.0)
+    plan = L.dedisp_plan_create(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list)
+    budget = 12 * L.dedisp_serve_slot_bytes([plan], C, WIDTHS)
+    res = {}
+    for mdl in (model, None):
+        srv = L.dedisp_serve_create([plan], C, WIDTHS, K, budget, model=mdl)
+        for k in range(3):
+            assert L.dedisp_serve_submit(srv, 0, k, _chunk(fb, k), L.dedisp_now_ns())
+        res[mdl is None] = sorted(_drain(srv, 3), key=lambda r: r["seq"])
+        srv.close()
+    bpc = fb.nchans // 4
+    H = plan.max_delay + WIDTHS[-1] - 1
+    for r, r0 in zip(res[False], res[True]):
+        assert r["flags"] & L.CHUNK_FALLBACK == 0 and r0["flags"] & L.CHUNK_FALLBACK
+        assert r["events"].tobytes() == r0["events"].tobytes() and r0["scores"] is None
+        k = r["seq"]
+        start = 0 if k == 0 else k * C - H
+        nsamps = C if k == 0 else C + H
+        inp = torch.from_numpy(fb.packed[start * bpc:(start + nsamps) * bpc].copy()).cuda()
+        nout = nsamps - plan.max_delay
+        ws = torch.empty(L.dedisp_workspace_bytes(plan, nsamps), dtype=torch.uint8, device="cuda")
+        out = torch.empty((plan.ndm, nout), dtype=torch.int16, device="cuda")
+        L.dedisp_execute(plan, inp, nsamps, out, ws)
+        pws = torch.empty(L.find_peaks_workspace_bytes(plan.ndm, nout, WIDTHS), dtype=torch.uint8,
+                          device="cuda")
+        evb = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+        n = L.find_peaks(out, plan.ndm, nout, WIDTHS, K, evb, (1 << 20) // 40, pws)
+        ev = L.events_from_buffer(evb, n)
+        # the chunk's events are the window's (times relative to t_abs0)
+        assert n == r["n_events"] and n > 0
+        assert ev.tobytes() == r["events"].tobytes()
+        tiles = torch.empty((n, 64, 256), dtype=torch.int16, device="cuda")
+        L.triage_tiles(out, plan.ndm, nout, WIDTHS, pws, evb, n, tiles)
+        sc = torch.empty(n, dtype=torch.float32, device="cuda")
+        L.triage_forward(model, tiles, n, scores=sc)
+        torch.cuda.synchronize()
+        log("chunk", k, "events", n, "scores", r["scores"][:4])
+        assert r["scores"] is not None and len(r["scores"]) == n
+        assert (sc.cpu().numpy() == r["scores"]).all()
