@@ -101,9 +101,8 @@ def main():
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: every beam and DM trial of this workload fits "
-              "one MI355X and this build has no multi-GPU path (see DESIGN.md for how it would "
-              "shard by beam and DM range).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: every beam and DM trial of this workload fits one "
+              "MI355X, and the library has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -7,7 +7,7 @@ events are thinned by per-width non-maximum suppression, labelled against
 the injections, and turned into 64-DM x 256-step tiles by the library's
 tile kernel.  The network is trained with the library's own forward,
 backward and Adam kernels.  The plain S/N detector (every candidate kept)
-is both the fallback and the judge: triage keeps a candidate when its score
+is both the fallback and the yardstick: triage keeps a candidate when its score
 reaches a threshold chosen on the validation beams so that recall stays
 within half a percent of the plain detector's.
 

@@ -3,7 +3,7 @@
 The committed network (trained on the GPU by the library's own kernels, see
 paper_1112_0065_amd/triage_train.py) scores the candidates of beams it never
 saw (seeds 800..863; training used 10000.., the score cut was chosen on
-600..679).  The plain detector keeps every candidate and is the judge:
+600..679).  The plain detector keeps every candidate and is the yardstick:
 triage must keep the recall over injected pulses within 1% of the plain
 detector's while passing far fewer false candidates."""
 import numpy as np
@@ -26,7 +26,7 @@ def test_trained_triage_keeps_recall_and_cuts_false_candidates():
     log("triage on unseen beams", r, "trained:", report["test"])
     assert r["recall_triage"] >= r["recall_plain"] - 0.01
     assert r["false_triage"] < 0.25 * r["false_plain"]
-    # the plain detector is the judge: the same cut with no network passes all
+    # the plain detector is the yardstick: with no network every candidate passes
     plain = T.evaluate(np.ones_like(sc), recs, tau)
     assert plain["recall_triage"] == plain["recall_plain"]
     assert plain["false_triage"] == plain["false_plain"]
