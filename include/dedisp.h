@@ -76,8 +76,13 @@ typedef struct triage_model_s* triage_model;
  * tsamp_s > 0: sampling interval.
  * dm_list: host, ndm finite values >= 0, non-decreasing.  Copied.
  * plan_out: host, receives the new plan.  The plan owns its device delay table
- *   and is immutable: it may be used from several streams at once as long as
- *   every call gets its own workspace.
+ *   and, per dedispersion tile shape, a table of LDS read offsets and shifts
+ *   (ndm*nchans uint32).  The default shape's table is built here; another
+ *   shape's is built, synchronously (host computation, device allocation and
+ *   upload), by the first call that uses it -- make that call outside any
+ *   stream capture.  Apart from that the plan is immutable: it may be used
+ *   from several streams and threads at once as long as every call gets its
+ *   own workspace.
  * Errors: INVALID_ARG, OUT_OF_MEMORY, HIP (device allocation / copy failed).
  * ------------------------------------------------------------------------ */
 dedisp_status dedisp_plan_create(int32_t nchans, double f_top_mhz, double df_mhz,
@@ -114,8 +119,9 @@ dedisp_status dedisp_execute(dedisp_plan plan, const uint8_t* in_2bit, int64_t n
 
 /* Tile shape of the dedispersion kernel: trials sharing one LDS tile
  * (4, 8, 16 or 32), 32-sample groups per lane (1 or 2; time tile = 2048 *
- * groups samples) and channels per LDS stage (multiple of 4, 4..128).  Every
- * supported shape gives bit-identical output; they differ only in speed. */
+ * groups samples) and channels per LDS stage (multiple of 4; the LDS holds
+ * two stages).  Every supported shape gives bit-identical output; they
+ * differ only in speed. */
 typedef struct {
     int32_t dms_per_block;
     int32_t groups;
@@ -129,9 +135,12 @@ int32_t dedisp_tile_candidates(dedisp_tile* out, int32_t cap);
 /* The tile shape dedisp_execute uses for this plan. */
 dedisp_status dedisp_default_tile(dedisp_plan plan, dedisp_tile* out);
 
-/* dedisp_execute with an explicit tile shape (host pointer `tile`).
- * Errors as dedisp_execute, plus INVALID_ARG for an unsupported shape and
- * UNSUPPORTED when its LDS tile does not fit for this plan. */
+/* dedisp_execute with an explicit tile shape (host pointer `tile`).  The
+ * first call with a shape builds the plan's offset table for it (see
+ * dedisp_plan_create).
+ * Errors as dedisp_execute, plus INVALID_ARG for an unsupported shape,
+ * UNSUPPORTED when its LDS tile does not fit for this plan and
+ * OUT_OF_MEMORY when its offset table cannot be allocated. */
 dedisp_status dedisp_execute_tile(dedisp_plan plan, const uint8_t* in_2bit, int64_t nsamps,
                                   void* out, dedisp_out_type out_type, void* workspace,
                                   const dedisp_tile* tile, dedisp_stream stream);
