@@ -26,8 +26,11 @@ dedisp_status check_widths(const int32_t* widths, int32_t nwidths, int64_t nout,
     if (nout - w_max + 1 < 1)
         return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "series of %lld samples shorter than width %d",
                     static_cast<long long>(nout), w_max);
-    if (nout - w_max + 1 >= (int64_t(1) << 31))
-        return fail(DEDISP_ERR_UNSUPPORTED, "series longer than 2^31 boxcar positions");
+    // the search kernels address a series row (plus one segment's halo) with
+    // 32-bit byte offsets
+    if ((nout + 16384 + w_max) * 4 >= (int64_t(1) << 31))
+        return fail(DEDISP_ERR_UNSUPPORTED, "series of %lld samples: rows must stay below 2^31 bytes",
+                    static_cast<long long>(nout));
     return DEDISP_OK;
 }
 

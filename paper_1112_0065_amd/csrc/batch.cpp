@@ -128,7 +128,7 @@ extern "C" dedisp_status dedisp_batch_create(const dedisp_plan* plans, int32_t n
     if (out_type != DEDISP_OUT_I32 && out_type != DEDISP_OUT_U16)
         return fail(DEDISP_ERR_INVALID_ARG, "bad out_type");
     dd::Widths W;
-    dedisp_status st = dd::check_widths_public(widths, nwidths, INT64_C(1) << 30, &W);
+    dedisp_status st = dd::check_widths_public(widths, nwidths, INT64_C(1) << 20, &W);
     if (st != DEDISP_OK) return st;
     uint32_t km;
     int ke;
@@ -257,7 +257,7 @@ extern "C" dedisp_status dedisp_batch_execute(dedisp_batch b, const uint8_t* con
         if (nsamps[i] - p->max_delay - w_max + 1 < 1)
             return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "beam %d: %lld samples", i,
                         static_cast<long long>(nsamps[i]));
-        if (nsamps[i] - p->max_delay - w_max + 1 >= (int64_t(1) << 31))
+        if ((nsamps[i] - p->max_delay + 16384 + w_max) * 4 >= (int64_t(1) << 31))
             return fail(DEDISP_ERR_UNSUPPORTED, "beam %d too long", i);
     }
     bool changed = !b->exec || b->k_in.size() != static_cast<size_t>(b->nbeams);

@@ -182,25 +182,42 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* w
 // Loads and LDS reads are issued in batches of kBatch per thread so that
 // their latencies overlap.
 constexpr int kBatch = 12;
+// Word 3 of a raw (unstrided) buffer resource on gfx9-family GPUs: 32-bit
+// data format, no swizzle; loads are range-checked against the byte count.
+constexpr int kRowRsrcWord3 = 0x00020000;
+
+// One sample of a series row through a buffer resource whose range is the
+// row: offsets outside it (negative ones wrap to huge) read as 0.
+__device__ __forceinline__ uint32_t row_load(__amdgpu_buffer_rsrc_t rs, int byte_off, uint16_t*) {
+    return __builtin_amdgcn_raw_buffer_load_b16(rs, byte_off, 0, 0);
+}
+__device__ __forceinline__ uint32_t row_load(__amdgpu_buffer_rsrc_t rs, int byte_off, int32_t*) {
+    return __builtin_amdgcn_raw_buffer_load_b32(rs, byte_off, 0, 0);
+}
 
 template <typename T>
 __device__ void load_prefix(const T* __restrict__ row, int64_t nout, int64_t first, int n,
                             uint32_t* pl, uint32_t* wave_tot, uint32_t* vmax = nullptr) {
-    // coalesced load of the raw values into pl[1..n)
+    // coalesced load of the raw values into pl[1..n); the launchers keep a
+    // row (and first + n) below 2^31 bytes
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<T*>(row), 0, static_cast<int>(nout * static_cast<int64_t>(sizeof(T))), kRowRsrcWord3);
+    const int off0 = static_cast<int>(first) * static_cast<int>(sizeof(T));
     uint32_t m = 0;
     for (int base = threadIdx.x; base < n - 1; base += kBatch * kThreads) {
         uint32_t v[kBatch];
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
             const int i = base + k * kThreads;
-            const int64_t t = first + i;
-            v[k] = (i < n - 1 && t >= 0 && t < nout) ? static_cast<uint32_t>(row[t]) : 0u;
+            v[k] = row_load(rs, off0 + i * static_cast<int>(sizeof(T)), static_cast<T*>(nullptr));
         }
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
             const int i = base + k * kThreads;
-            if (i < n - 1) pl[i + 1] = v[k];
-            m = max(m, v[k]);
+            if (i < n - 1) {
+                pl[i + 1] = v[k];
+                m = max(m, v[k]);
+            }
         }
     }
     if (vmax) {
@@ -509,10 +526,22 @@ __global__ __launch_bounds__(kThreads) void series_threshold_kernel(int nseries,
     if (s >= nseries) return;
     uint64_t s1 = 0;
     u128 s2 = 0;
-    for (int g = 0; g < nseg; ++g) {
-        const int64_t idx = static_cast<int64_t>(s) * nseg + g;
-        s1 += ws.part_s1[idx];
-        s2 += static_cast<u128>(ws.part_s2lo[idx]) | (static_cast<u128>(ws.part_s2hi[idx]) << 64);
+    // partials in batches of 8 loads (independent, so their latencies overlap)
+    for (int g0 = 0; g0 < nseg; g0 += 8) {
+        uint64_t p1[8], plo[8], phi[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t idx = static_cast<int64_t>(s) * nseg + g0 + k;
+            const bool in = g0 + k < nseg;
+            p1[k] = in ? ws.part_s1[idx] : 0;
+            plo[k] = in ? ws.part_s2lo[idx] : 0;
+            phi[k] = in ? ws.part_s2hi[idx] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            s1 += p1[k];
+            s2 += static_cast<u128>(plo[k]) | (static_cast<u128>(phi[k]) << 64);
+        }
     }
     const uint64_t n = static_cast<uint64_t>(nbx);
     const u128 d = static_cast<u128>(n) * s2 - static_cast<u128>(s1) * s1;

@@ -397,7 +397,7 @@ extern "C" dedisp_status dedisp_serve_create(const dedisp_plan* plans, int32_t n
             return fail(DEDISP_ERR_INVALID_ARG, "all plans must be on one device");
     }
     dd::Widths W;
-    dedisp_status st = dd::check_widths_public(widths, nwidths, INT64_C(1) << 30, &W);
+    dedisp_status st = dd::check_widths_public(widths, nwidths, INT64_C(1) << 20, &W);
     if (st != DEDISP_OK) return st;
     uint32_t km;
     int ke;
@@ -422,6 +422,11 @@ extern "C" dedisp_status dedisp_serve_create(const dedisp_plan* plans, int32_t n
         delete s;
         return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "chunk of %lld samples <= overlap %lld",
                     static_cast<long long>(chunk_nsamps), static_cast<long long>(s->H));
+    }
+    if ((s->C + s->H + 16384 + w_max) * 4 >= (int64_t(1) << 31)) {
+        delete s;
+        return fail(DEDISP_ERR_UNSUPPORTED, "chunk of %lld samples too long",
+                    static_cast<long long>(chunk_nsamps));
     }
     s->deadline_ns = static_cast<double>(s->C) * plans[0]->tsamp * 1e9;
     s->nl = dd::levels_for(nchans);
