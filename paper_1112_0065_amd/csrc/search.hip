@@ -360,16 +360,6 @@ __device__ __forceinline__ void stats_full_nw(uint32_t* pl, const dd::Widths& W,
         s2[wi] = 0;
         woff[wi] = W.w[wi];
     }
-    // Sum of the segment's boxcars by telescoping: with P the running sums,
-    //   sum_{j<L} (P[j+1+w] - P[j+1]) = sum_{k=1..w} (P[L+k] - P[k]),
-    // each term a sum of L samples (below 2^32 by the caller's check).
-    constexpr int L = kPerThread * kThreads;
-    for (int k = threadIdx.x + 1; k <= woff[NW - 1]; k += kThreads) {
-        const uint64_t dk = pl[L + k] - pl[k];
-#pragma unroll
-        for (int wi = 0; wi < NW; ++wi)
-            if (k <= woff[wi]) s1[wi] += dk;
-    }
     const uint32_t* base = pl + 1 + threadIdx.x;
 #pragma unroll 4
     for (int j = 0; j < kPerThread; ++j) {
@@ -380,6 +370,17 @@ __device__ __forceinline__ void stats_full_nw(uint32_t* pl, const dd::Widths& W,
             s2[wi] += static_cast<uint64_t>(b) * b;
             mx[wi] = max(mx[wi], b);
         }
+    }
+    // Sum of the segment's boxcars by telescoping: with P the running sums,
+    //   sum_{j<L} (P[j+1+w] - P[j+1]) = sum_{k=1..w} (P[L+k] - P[k]),
+    // each term a sum of L samples (below 2^32 by the caller's check).
+    // (After the main loop, so that its registers are free there.)
+    constexpr int L = kPerThread * kThreads;
+    for (int k = threadIdx.x + 1; k <= woff[NW - 1]; k += kThreads) {
+        const uint64_t dk = pl[L + k] - pl[k];
+#pragma unroll
+        for (int wi = 0; wi < NW; ++wi)
+            if (k <= woff[wi]) s1[wi] += dk;
     }
     __syncthreads();   // the running sums are no longer needed: reuse pl
     uint64_t* r = reinterpret_cast<uint64_t*>(pl);
