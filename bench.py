@@ -222,6 +222,8 @@ def main():
         print("13-beam batch ...", file=sys.stderr, flush=True)
         rec["multibeam"] = bench_multibeam(args)
         rec["rtf_13beam"] = rec["multibeam"]["rtf_batch"]
+    print("13-beam coincidence mask ...", file=sys.stderr, flush=True)
+    rec["rfi_mask"] = bench_rfi_mask(args)
     if not args.no_serve:
         print("13-beam streaming at the real-time rate ...", file=sys.stderr, flush=True)
         rec["serve"] = bench_serve(args)
@@ -341,6 +343,38 @@ def bench_serve(args):
             "batches": st["batches"], "mean_batch": st["mean_batch"], "max_batch": st["max_batch"],
             "slots": st["slots"], "busy_retries": busy, "wall_s": wall,
             "data": "4 fast-noise chunk payloads cycled over beams and sequence numbers"}
+
+
+def bench_rfi_mask(args):
+    """Multibeam coincidence mask over 13 beams x 2^19 samples x 1024
+    channels (3 sigma in >= 4 beams).  HBM roofline: the packed inputs are
+    read once (13 x 128 MiB); the zero-DM series is written, read by the
+    statistics pass and read again by the vote (4 B x 3 per beam-sample); the
+    mask is written (1 B per sample)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1112_0065_amd import _lib as L
+
+    nsamps, nb = 1 << 19, 13
+    pool = synth.fast_chunk(500, nsamps, npulses=4)
+    ins = [torch.from_numpy(pool).to("cuda") for _ in range(nb)]
+    ws = torch.empty(L.dedisp_rfi_mask_workspace_bytes(nb, nsamps), dtype=torch.uint8,
+                     device="cuda")
+    mask = torch.empty(nsamps, dtype=torch.uint8, device="cuda")
+    L.dedisp_rfi_mask(ins, 1024, nsamps, 3.0, 4, mask, ws)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        n = L.dedisp_rfi_mask(ins, 1024, nsamps, 3.0, 4, mask, ws)
+    dt = (time.perf_counter() - t0) / reps
+    alg = nb * nsamps * (256 + 12) + nsamps
+    return {"beams": nb, "nsamps": nsamps, "ms": dt * 1e3, "masked": n,
+            "algorithmic_bytes": alg, "achieved_GBps": alg / dt / 1e9,
+            "hbm_frac": alg / dt / 8e12,
+            "note": "includes the host synchronisation of the call; the same payload in every beam"}
 
 
 def bench_serve_unpaced(args):

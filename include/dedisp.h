@@ -350,6 +350,36 @@ int64_t dedisp_percentile_ns(const int64_t* sorted, int64_t n, double q);
 int32_t dedisp_serve_admission(size_t budget, size_t resident, size_t slot_bytes);
 
 /* ------------------------------------------------------------------------
+ * Multibeam coincidence RFI mask (section 2.1: interference is not localised,
+ * so the beams of the multibeam receiver act as reference antennas for one
+ * another; a sample where enough beams exceed a S/N threshold is flagged).
+ *
+ * For each beam b the zero-DM series z_b[t] = sum_c level_b(c, t) over
+ * 0 <= t < nsamps (all beams cover the same samples), its exact sums
+ * S1 = sum z, S2 = sum z^2, D = nsamps*S2 - S1^2, and the cut level
+ * thr_b = ceil((S1 + isqrt(floor(k^2 D)) + 1) / nsamps) with k the float
+ * value of k_sigma (z >= thr_b <=> (z - mean)/sigma > k, population sigma;
+ * D == 0: the beam never exceeds).  mask[t] = 1 when at least min_beams
+ * beams have z_b[t] >= thr_b, else 0.
+ *
+ * in_2bit: host array of nbeams device pointers, each nsamps*nchans/4 bytes
+ *   laid out as for dedisp_execute.  1 <= nbeams <= 64; nchans a multiple of
+ *   4 in [4, 21844]; 1 <= nsamps < 2^31.  k_sigma finite, > 0; min_beams >= 1.
+ * mask: device, nsamps bytes (0 or 1).  n_masked: host, number of ones.
+ * workspace: device, >= dedisp_rfi_mask_workspace_bytes(nbeams, nsamps)
+ *   bytes, 256-byte aligned; it starts with the zero-DM series, int32
+ *   [nbeams][nsamps], which dedisp_rfi_mask_read_stats copies out together
+ *   with the cut levels (int64 [nbeams], -1 where D == 0).
+ * Synchronises `stream`.  Errors: INVALID_ARG, HIP.
+ * ------------------------------------------------------------------------ */
+size_t dedisp_rfi_mask_workspace_bytes(int32_t nbeams, int64_t nsamps);
+dedisp_status dedisp_rfi_mask(const uint8_t* const* in_2bit, int32_t nbeams, int32_t nchans,
+                              int64_t nsamps, float k_sigma, int32_t min_beams, uint8_t* mask,
+                              int64_t* n_masked, void* workspace, dedisp_stream stream);
+dedisp_status dedisp_rfi_mask_read_stats(const void* workspace, int32_t nbeams, int64_t nsamps,
+                                         int32_t* zero_dm, int64_t* thr, dedisp_stream stream);
+
+/* ------------------------------------------------------------------------
  * Learned triage (section 2.1: interference can swamp detection with false
  * positives; a small network scores candidates so that the plain S/N
  * detector's events can be filtered).  Candidate tile of an event: 64 DM

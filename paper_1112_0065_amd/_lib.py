@@ -96,6 +96,9 @@ def lib() -> C.CDLL:
         "dedisp_batch_info": (i32, [vp, P(_Tile), P(i32), P(i32)]),
         "dedisp_batch_destroy": (i32, [vp]),
         "dedisp_autotune": (i32, [vp, i64, i32, C.c_char_p, P(_Tile), P(i32)]),
+        "dedisp_rfi_mask_workspace_bytes": (sz, [i32, i64]),
+        "dedisp_rfi_mask": (i32, [P(vp), i32, i32, i64, f32, i32, vp, P(i64), vp, vp]),
+        "dedisp_rfi_mask_read_stats": (i32, [vp, i32, i64, P(i32), P(i64), vp]),
         "dedisp_serve_slot_bytes": (sz, [P(vp), i32, i64, P(i32), i32]),
         "dedisp_serve_create": (i32, [P(vp), i32, i64, P(i32), i32, f32, sz, vp, P(vp)]),
         "dedisp_serve_submit": (i32, [vp, i32, i64, vp, i64]),
@@ -325,6 +328,37 @@ def events_from_buffer(buf, n: int) -> np.ndarray:
     if hasattr(raw, "cpu"):
         raw = raw.cpu().numpy()
     return np.frombuffer(np.asarray(raw, dtype=np.uint8).tobytes(), dtype=EVENT_DTYPE, count=n)
+
+
+# ---------------------------------------------------------------------------
+# Multibeam coincidence RFI mask
+# ---------------------------------------------------------------------------
+
+def dedisp_rfi_mask_workspace_bytes(nbeams: int, nsamps: int) -> int:
+    return int(lib().dedisp_rfi_mask_workspace_bytes(int(nbeams), int(nsamps)))
+
+
+def dedisp_rfi_mask(inputs, nchans: int, nsamps: int, k_sigma: float, min_beams: int, mask,
+                    workspace, stream=None) -> int:
+    """inputs: device tensors (one per beam); mask: device uint8 [nsamps].
+    Returns the number of masked samples (synchronises)."""
+    arr = (C.c_void_p * len(inputs))(*[_ptr(t) for t in inputs])
+    n = C.c_int64()
+    _check(lib().dedisp_rfi_mask(arr, len(inputs), int(nchans), int(nsamps), float(k_sigma),
+                                 int(min_beams), _ptr(mask), C.byref(n), _ptr(workspace),
+                                 _stream(stream)))
+    return int(n.value)
+
+
+def dedisp_rfi_mask_read_stats(workspace, nbeams: int, nsamps: int, stream=None):
+    """(zero-DM series int32 [nbeams][nsamps], cut levels int64 [nbeams])."""
+    z = np.empty((nbeams, nsamps), np.int32)
+    thr = np.empty(nbeams, np.int64)
+    _check(lib().dedisp_rfi_mask_read_stats(_ptr(workspace), int(nbeams), int(nsamps),
+                                            z.ctypes.data_as(C.POINTER(C.c_int32)),
+                                            thr.ctypes.data_as(C.POINTER(C.c_int64)),
+                                            _stream(stream)))
+    return z, thr
 
 
 # ---------------------------------------------------------------------------

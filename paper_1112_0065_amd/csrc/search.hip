@@ -24,138 +24,12 @@
 #include <cmath>
 
 #include "dedisp_internal.hpp"
+#include "intmath.hpp"
 #include "search_internal.hpp"
 
 namespace {
 
 constexpr int kThreads = 256;
-using u128 = unsigned __int128;
-
-struct u256 {
-    uint64_t w[4];
-};
-
-__device__ __forceinline__ u256 u256_from(u128 x) {
-    return u256{{static_cast<uint64_t>(x), static_cast<uint64_t>(x >> 64), 0, 0}};
-}
-
-// a * b for a < 2^128, b < 2^64.
-__device__ __forceinline__ u256 u256_mul_u64(u128 a, uint64_t b) {
-    const uint64_t a0 = static_cast<uint64_t>(a), a1 = static_cast<uint64_t>(a >> 64);
-    const u128 p0 = static_cast<u128>(a0) * b;
-    const u128 p1 = static_cast<u128>(a1) * b + (p0 >> 64);
-    return u256{{static_cast<uint64_t>(p0), static_cast<uint64_t>(p1), static_cast<uint64_t>(p1 >> 64), 0}};
-}
-
-__device__ __forceinline__ u256 u256_shr(u256 a, int s) {
-    u256 r{{0, 0, 0, 0}};
-    const int q = s >> 6, b = s & 63;
-    for (int i = 0; i < 4; ++i) {
-        const int j = i + q;
-        if (j < 4) {
-            uint64_t v = a.w[j] >> b;
-            if (b && j + 1 < 4) v |= a.w[j + 1] << (64 - b);
-            r.w[i] = v;
-        }
-    }
-    return r;
-}
-
-__device__ __forceinline__ u256 u256_shl(u256 a, int s) {
-    u256 r{{0, 0, 0, 0}};
-    const int q = s >> 6, b = s & 63;
-    for (int i = 3; i >= 0; --i) {
-        const int j = i - q;
-        if (j >= 0) {
-            uint64_t v = a.w[j] << b;
-            if (b && j - 1 >= 0) v |= a.w[j - 1] >> (64 - b);
-            r.w[i] = v;
-        }
-    }
-    return r;
-}
-
-__device__ __forceinline__ bool u256_ge(const u256& a, const u256& b) {
-    for (int i = 3; i >= 0; --i)
-        if (a.w[i] != b.w[i]) return a.w[i] > b.w[i];
-    return true;
-}
-
-__device__ __forceinline__ u256 u256_sub(u256 a, const u256& b) {
-    uint64_t borrow = 0;
-    for (int i = 0; i < 4; ++i) {
-        const uint64_t x = a.w[i], y = b.w[i];
-        const uint64_t d = x - y - borrow;
-        borrow = (x < y) || (x - y < borrow) ? 1 : 0;
-        a.w[i] = d;
-    }
-    return a;
-}
-
-__device__ __forceinline__ u256 u256_add(u256 a, const u256& b) {
-    uint64_t carry = 0;
-    for (int i = 0; i < 4; ++i) {
-        const uint64_t s = a.w[i] + b.w[i];
-        const uint64_t c1 = s < a.w[i];
-        const uint64_t s2 = s + carry;
-        const uint64_t c2 = s2 < s;
-        a.w[i] = s2;
-        carry = c1 | c2;
-    }
-    return a;
-}
-
-// floor(sqrt(x)), digit-by-digit (binary restoring method).
-__device__ u256 u256_isqrt(u256 x) {
-    u256 res{{0, 0, 0, 0}};
-    u256 bit{{0, 0, 0, 0}};
-    // highest power of four <= x
-    int top = -1;
-    for (int i = 3; i >= 0 && top < 0; --i)
-        if (x.w[i]) top = 64 * i + 63 - __builtin_clzll(x.w[i]);
-    if (top < 0) return res;
-    const int p = top & ~1;
-    bit.w[p >> 6] = uint64_t(1) << (p & 63);
-    while (bit.w[0] | bit.w[1] | bit.w[2] | bit.w[3]) {
-        const u256 t = u256_add(res, bit);
-        if (u256_ge(x, t)) {
-            x = u256_sub(x, t);
-            res = u256_add(u256_shr(res, 1), bit);
-        } else {
-            res = u256_shr(res, 1);
-        }
-        bit = u256_shr(bit, 2);
-    }
-    return res;
-}
-
-// floor(a / b), a < 2^128, b >= 1 (shift-subtract).
-__device__ u128 u128_div_u64(u128 a, uint64_t b) {
-    u128 q = 0, r = 0;
-    for (int i = 127; i >= 0; --i) {
-        r = (r << 1) | ((a >> i) & 1);
-        if (r >= b) {
-            r -= b;
-            q |= static_cast<u128>(1) << i;
-        }
-    }
-    return q;
-}
-
-// Round-to-nearest-even conversion of an unsigned 128-bit integer.
-__device__ double u128_to_double(u128 x) {
-    if ((x >> 64) == 0) return static_cast<double>(static_cast<uint64_t>(x));
-    const uint64_t hi = static_cast<uint64_t>(x >> 64);
-    const int lz = __builtin_clzll(hi);
-    const int nbits = 128 - lz;          // 65..128
-    const int drop = nbits - 53;
-    u128 m = x >> drop;                  // 53 significant bits
-    const u128 rem = x - (m << drop);
-    const u128 half = static_cast<u128>(1) << (drop - 1);
-    if (rem > half || (rem == half && (m & 1))) m += 1;
-    return ldexp(static_cast<double>(static_cast<uint64_t>(m)), drop);
-}
-
 // ----------------------------------------------------------------------------
 // Block-level helpers.
 // ----------------------------------------------------------------------------
@@ -544,30 +418,16 @@ __global__ __launch_bounds__(kThreads) void series_threshold_kernel(int nseries,
             s2 += static_cast<u128>(plo[k]) | (static_cast<u128>(phi[k]) << 64);
         }
     }
-    const uint64_t n = static_cast<uint64_t>(nbx);
-    const u128 d = static_cast<u128>(n) * s2 - static_cast<u128>(s1) * s1;
     ws.s1[s] = s1;
     ws.s2lo[s] = static_cast<uint64_t>(s2);
     ws.s2hi[s] = static_cast<uint64_t>(s2 >> 64);
-    if (d == 0) {
+    u128 d = 0;
+    const int64_t thr = cut_level(static_cast<uint64_t>(nbx), s1, s2, kmant, kexp2, &d);
+    if (thr < 0) {
         ws.thr[s] = -1;
         ws.thr32[s] = 0xFFFFFFFFu;
         ws.sqrt_d[s] = 0.0;
         return;
-    }
-    // floor(k^2 D) with k = kmant * 2^kexp2 (kexp2 <= 0): (kmant^2 D) >> -2 kexp2
-    const u256 kd = u256_mul_u64(d, static_cast<uint64_t>(kmant) * kmant);
-    const u256 q = kexp2 >= 0 ? u256_shl(kd, 2 * kexp2) : u256_shr(kd, -2 * kexp2);
-    const u256 r = u256_isqrt(q);
-    // lmin = isqrt + 1 < 2^128 here; B_thr = ceil((S1 + lmin) / n)
-    const u128 lmin = (static_cast<u128>(r.w[1]) << 64 | r.w[0]) + 1;
-    int64_t thr;
-    if (r.w[2] | r.w[3] | (r.w[1] >> 62)) {
-        thr = INT64_MAX;
-    } else {
-        const u128 num = static_cast<u128>(s1) + lmin;
-        const u128 b = u128_div_u64(num + (n - 1), n);
-        thr = (b >> 62) ? INT64_MAX : static_cast<int64_t>(b);
     }
     ws.thr[s] = thr;
     ws.thr32[s] = thr > 0xFFFFFFFFll ? 0xFFFFFFFFu : static_cast<uint32_t>(thr);

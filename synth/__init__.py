@@ -347,6 +347,41 @@ def make_rfi_beam(seed: int, nsamps: int = 1 << 17, dm_max: float = 1000.0,
                                periodic_window=[win0, win1]))
 
 
+def make_coincidence_beams(seed: int, nbeams: int = NBEAMS, nsamps: int = 1 << 17,
+                           nchans: int = 1024, npulses: int = 2, impulse_rate: float = 2.0,
+                           dm_max: float = 1000.0):
+    """Beams of one receiver over the same samples, for the coincidence mask:
+    independent noise and dispersed pulses per beam (survey recipe), plus
+    broadband zero-DM impulses common to all beams -- Poisson, `impulse_rate`
+    per second, width U{1..8} samples -- whose amplitude differs per beam,
+    U(0.5, 3) sigma per channel.  Returns (list of packed arrays, impulses,
+    amplitudes [impulse][beam], pulses per beam)."""
+    root = np.random.default_rng(np.random.SeedSequence([seed, 77]))
+    df = -400.0 / nchans
+    nimp = int(root.poisson(impulse_rate * nsamps * TSAMP))
+    imps = [Impulse(int(root.integers(0, nsamps - 8)), int(root.integers(1, 9)), 0.0)
+            for _ in range(nimp)]
+    amps = root.uniform(0.5, 3.0, (nimp, nbeams))
+    packed, pulses_all = [], []
+    for b in range(nbeams):
+        rng_n, rng_p = _streams(seed * 1000 + b)
+        pulses = _snr_pulses(rng_p, npulses, nchans, nsamps, 0.0, dm_max, F_TOP, df, TSAMP)
+        offs = [sky_arrival_offsets(nchans, F_TOP, df, TSAMP, p.dm) for p in pulses]
+        pulse_inj = _float_pulse_injector(pulses, offs)
+
+        def inject(x, t_lo, b=b, pulse_inj=pulse_inj):
+            n = x.shape[0]
+            pulse_inj(x, t_lo)
+            for i, im in enumerate(imps):
+                lo, hi = max(im.t, t_lo), min(im.t + im.width, t_lo + n)
+                if lo < hi:
+                    x[lo - t_lo:hi - t_lo, :] += amps[i, b]
+
+        packed.append(_noise_levels(rng_n, nsamps, nchans, inject))
+        pulses_all.append(pulses)
+    return packed, imps, amps, pulses_all
+
+
 def fast_levels(rng: np.random.Generator, nsamps: int, nchans: int) -> np.ndarray:
     """2-bit levels with the quantiser's level probabilities (0.163543,
     0.336457, 0.336457, 0.163543) drawn directly from 16-bit uniforms -- a
