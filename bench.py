@@ -216,6 +216,24 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    # baseline removal (running mean, radius 2048) of the survey series: one
+    # read and one write of the uint16 rows
+    R = 2048
+    flat = torch.empty((ndm, nout - 2 * R), dtype=torch.int16, device="cuda")
+    L.baseline_remove(out, ndm, nout, R, 3 * fb.nchans, flat)
+    torch.cuda.synchronize()
+    b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b0.record()
+    for _ in range(10):
+        L.baseline_remove(out, ndm, nout, R, 3 * fb.nchans, flat)
+    b1.record()
+    b1.synchronize()
+    bl_ms = b0.elapsed_time(b1) / 10
+    bl_bytes = ndm * nout * 2 + ndm * (nout - 2 * R) * 2
+    rec["baseline"] = {"radius": R, "ms": bl_ms, "algorithmic_bytes": bl_bytes,
+                       "achieved_GBps": bl_bytes / (bl_ms * 1e-3) / 1e9,
+                       "hbm_frac": bl_bytes / (bl_ms * 1e-3) / 8e12}
+    del flat
     del out, ws, pws, evb, inp
     torch.cuda.empty_cache()
     if not args.no_multibeam:

@@ -178,6 +178,26 @@ dedisp_status boxcar_filter(const void* in, dedisp_out_type in_type, int32_t ndm
                             int32_t dm_first, int32_t dm_count, int32_t* out,
                             dedisp_stream stream);
 
+/* ------------------------------------------------------------------------
+ * Baseline (red-noise) removal by a running mean (section 2.3, first
+ * paragraph), exact in integers:
+ *   out[d][t] = in[d][t + R] - floor(sum_{j=t}^{t+2R} in[d][j] / (2R + 1)) + offset
+ * for 0 <= t < nout - 2R (windows wholly inside the series).
+ *
+ * in: device [ndm][nout] series (int32 or uint16 per in_type; values >= 0
+ *   and any 2R + 1 of them summing below 2^31 -- always so for uint16).
+ * out: device [ndm][nout - 2R], int32 or uint16 per out_type, row stride
+ *   nout - 2R.  The caller chooses offset so that the results fit out_type
+ *   (for a dedispersed 2-bit series with values in [0, 3 nchans] and uint16
+ *   output: offset = 3 nchans, needs 6 nchans <= 65535).  A constant offset
+ *   changes no S/N: the result feeds boxcar_filter / find_peaks directly.
+ * 0 <= radius <= 8192.  Errors: INVALID_ARG, TOO_FEW_SAMPLES, UNSUPPORTED,
+ *   HIP.  Asynchronous.
+ * ------------------------------------------------------------------------ */
+dedisp_status baseline_remove(const void* in, dedisp_out_type in_type, int32_t ndm, int64_t nout,
+                              int32_t radius, int32_t offset, void* out, dedisp_out_type out_type,
+                              dedisp_stream stream);
+
 /* Bytes of device workspace find_peaks needs. 0 on invalid arguments. */
 size_t find_peaks_workspace_bytes(int32_t ndm, int64_t nout, const int32_t* widths,
                                   int32_t nwidths);

@@ -25,8 +25,10 @@ from .sigma_cut import (series_stats, threshold_level, snr_value, exact_k,
 from .peaks import find_runs, find_events, EVENT_FIELDS
 from .pipeline import search
 from .coincidence import zero_dm_series, rfi_mask, binomial_tail
+from .baseline import baseline_remove
 
 __all__ = [
+    "baseline_remove",
     "zero_dm_series", "rfi_mask", "binomial_tail",
     "K_DM", "channel_freqs", "delay_table", "max_delay", "nearest_tie_distance",
     "unpack_2bit", "dedisperse", "brute_dedisperse", "prefix_sum", "boxcar",

@@ -97,6 +97,7 @@ def lib() -> C.CDLL:
         "dedisp_batch_destroy": (i32, [vp]),
         "dedisp_autotune": (i32, [vp, i64, i32, C.c_char_p, P(_Tile), P(i32)]),
         "dedisp_rfi_mask_workspace_bytes": (sz, [i32, i64]),
+        "baseline_remove": (i32, [vp, i32, i32, i64, i32, i32, vp, i32, vp]),
         "dedisp_rfi_mask": (i32, [P(vp), i32, i32, i64, f32, i32, vp, P(i64), vp, vp]),
         "dedisp_rfi_mask_read_stats": (i32, [vp, i32, i64, P(i32), P(i64), vp]),
         "dedisp_serve_slot_bytes": (sz, [P(vp), i32, i64, P(i32), i32]),
@@ -283,6 +284,14 @@ def boxcar_filter(series, ndm: int, nout: int, widths, dm_first: int, dm_count: 
     _check(lib().boxcar_filter(_ptr(series), _out_type(series), int(ndm), int(nout), w,
                                len(widths), int(dm_first), int(dm_count), _ptr(out),
                                _stream(stream)))
+
+
+def baseline_remove(series, ndm: int, nout: int, radius: int, offset: int, out, stream=None):
+    """out[d][t] = series[d][t+R] - floor(window sum / (2R+1)) + offset over
+    nout - 2R positions; series and out are device tensors (int16 = uint16
+    bits, or int32)."""
+    _check(lib().baseline_remove(_ptr(series), _out_type(series), int(ndm), int(nout), int(radius),
+                                 int(offset), _ptr(out), _out_type(out), _stream(stream)))
 
 
 def find_peaks_workspace_bytes(ndm: int, nout: int, widths) -> int:

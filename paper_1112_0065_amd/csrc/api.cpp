@@ -215,6 +215,26 @@ extern "C" dedisp_status boxcar_filter(const void* in, dedisp_out_type in_type, 
     return DEDISP_OK;
 }
 
+extern "C" dedisp_status baseline_remove(const void* in, dedisp_out_type in_type, int32_t ndm,
+                                         int64_t nout, int32_t radius, int32_t offset, void* out,
+                                         dedisp_out_type out_type, dedisp_stream stream) {
+    if (!in || !out) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
+    if (!valid_type(in_type) || !valid_type(out_type))
+        return fail(DEDISP_ERR_INVALID_ARG, "bad in_type or out_type");
+    if (ndm < 1 || ndm > 65535) return fail(DEDISP_ERR_INVALID_ARG, "need 1 <= ndm <= 65535");
+    if (radius < 0 || radius > 8192)
+        return fail(DEDISP_ERR_INVALID_ARG, "radius %d outside [0, 8192]", radius);
+    if (nout - 2 * static_cast<int64_t>(radius) < 1)
+        return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "series of %lld samples, window of %d",
+                    static_cast<long long>(nout), 2 * radius + 1);
+    if ((nout + 8192 + 2 * static_cast<int64_t>(radius) + 1) * 4 >= (int64_t(1) << 31))
+        return fail(DEDISP_ERR_UNSUPPORTED, "series rows must stay below 2^31 bytes");
+    DD_HIP(dd::launch_baseline(in, in_type == DEDISP_OUT_U16, ndm, nout, radius, offset, out,
+                               out_type == DEDISP_OUT_U16, stream));
+    dd::clear_error();
+    return DEDISP_OK;
+}
+
 extern "C" size_t find_peaks_workspace_bytes(int32_t ndm, int64_t nout, const int32_t* widths,
                                              int32_t nwidths) {
     dd::Widths W;

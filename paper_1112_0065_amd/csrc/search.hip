@@ -160,6 +160,35 @@ __global__ __launch_bounds__(kThreads) void boxcar_kernel(const T* __restrict__ 
     }
 }
 
+// Baseline (red-noise) removal by a running mean (paper section 2.3, first
+// paragraph): for output position t (input position t + R),
+//   out[t] = in[t + R] - floor((sum_{j=t}^{t+2R} in[j]) / (2R + 1)) + offset,
+// integer and exact; the running sum comes from the same LDS prefix scan as
+// the boxcars.  Grid (segments of Lb outputs, DMs).
+template <typename T, typename U>
+__global__ __launch_bounds__(kThreads) void baseline_kernel(const T* __restrict__ in, int64_t nout,
+                                                            int64_t nres, int radius, int offset,
+                                                            int Lb, uint64_t magic, int shift,
+                                                            U* __restrict__ out) {
+    extern __shared__ uint32_t pl[];
+    __shared__ uint32_t wave_tot[kThreads / 64];
+    const int d = blockIdx.y;
+    const int64_t s0 = static_cast<int64_t>(blockIdx.x) * Lb;
+    const int win = 2 * radius + 1;
+    const int n = Lb + win;   // running sums pl[0..n)
+    load_prefix(in + static_cast<int64_t>(d) * nout, nout, s0, n, pl, wave_tot);
+    U* o = out + static_cast<int64_t>(d) * nres;
+    for (int i = threadIdx.x; i < Lb; i += kThreads) {
+        const int64_t t = s0 + i;
+        if (t >= nres) break;
+        const uint32_t sum = pl[i + win] - pl[i];
+        const uint32_t x = pl[i + radius + 1] - pl[i + radius];
+        // floor(sum / win) as a multiply and shift (exact for sum < 2^31)
+        const uint32_t mean = static_cast<uint32_t>((static_cast<uint64_t>(sum) * magic) >> shift);
+        o[t] = static_cast<U>(static_cast<int32_t>(x) - static_cast<int32_t>(mean) + offset);
+    }
+}
+
 // Pass 1: per (width, DM, segment) partial sums of B and B^2 and the largest B.
 // Per thread and width at most L/256 <= 32 positions are summed in registers.
 // When every B of the block's window is below 2^26 (the largest raw value
@@ -821,6 +850,37 @@ hipError_t launch_boxcar(const void* in, int in_u16, int ndm, int64_t nout, cons
         hipLaunchKernelGGL(boxcar_kernel<int32_t>, grid, dim3(kThreads), lds, s,
                            static_cast<const int32_t*>(in), nout, nbx, W, dm_first, L, out, dm_count);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_baseline(const void* in, int in_u16, int ndm, int64_t nout, int radius,
+                           int offset, void* out, int out_u16, hipStream_t s) {
+    const int64_t nres = nout - 2 * static_cast<int64_t>(radius);
+    const int Lb = 8192;
+    // floor(n / w) = (n * M) >> k with k = 31 + ceil(log2 w), M = ceil(2^k / w):
+    // writing M w = 2^k + e (0 <= e < w), n M / 2^k = n / w + n e / (w 2^k), and
+    // n e < 2^31 * 2^ceil(log2 w) = 2^k for n < 2^31, so the extra term stays
+    // below 1/w and cannot carry past the next integer; n M < 2^63.
+    const uint32_t win = 2u * static_cast<uint32_t>(radius) + 1u;
+    int lg = 0;
+    while ((1u << lg) < win) ++lg;
+    const int shift = 31 + lg;
+    const uint64_t magic = ((uint64_t(1) << shift) + win - 1) / win;
+    const size_t lds = static_cast<size_t>(Lb + 2 * radius + 1) * 4;
+    const dim3 grid(static_cast<unsigned>((nres + Lb - 1) / Lb), static_cast<unsigned>(ndm));
+#define DD_BL(T, U)                                                                            \
+    {                                                                                          \
+        hipError_t e = set_lds_limit(reinterpret_cast<const void*>(baseline_kernel<T, U>), lds); \
+        if (e != hipSuccess) return e;                                                         \
+        hipLaunchKernelGGL((baseline_kernel<T, U>), grid, dim3(kThreads), lds, s,              \
+                           static_cast<const T*>(in), nout, nres, radius, offset, Lb, magic,   \
+                           shift, static_cast<U*>(out));                                       \
+    }
+    if (in_u16 && out_u16) DD_BL(uint16_t, uint16_t)
+    else if (in_u16) DD_BL(uint16_t, int32_t)
+    else if (out_u16) DD_BL(int32_t, uint16_t)
+    else DD_BL(int32_t, int32_t)
+#undef DD_BL
     return hipGetLastError();
 }
 

@@ -56,6 +56,8 @@ int segment_length(int w_max);
 PeaksLayout peaks_layout(int ndm, int64_t nout, const Widths& W);
 PeaksWs peaks_ws(void* base, const PeaksLayout& lay);
 
+hipError_t launch_baseline(const void* in, int in_u16, int ndm, int64_t nout, int radius,
+                           int offset, void* out, int out_u16, hipStream_t s);
 hipError_t launch_boxcar(const void* in, int in_u16, int ndm, int64_t nout, const Widths& W,
                          int dm_first, int dm_count, int32_t* out, hipStream_t s);
 // Stats, thresholds, run-start counts and their scan (total in ws.total).

@@ -102,3 +102,20 @@ def test_bitslice_helpers_exact(tmp_path):
     assert r.returncode == 0, r.stderr
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0 and "ALL OK" in r.stdout, r.stdout
+
+
+def test_baseline_division_by_multiply_is_exact():
+    """The running-mean kernel divides the window sum n < 2^31 by the window
+    w = 2R + 1 <= 16385 as (n * M) >> k, k = 31 + ceil(log2 w),
+    M = ceil(2^k / w); check the identity for every w at the extreme and
+    random n, and that n * M stays below 2^63."""
+    import random
+    rnd = random.Random(7)
+    for w in range(1, 16386, 2):
+        lg = (w - 1).bit_length()
+        k = 31 + lg
+        m = ((1 << k) + w - 1) // w
+        for n in [0, 1, w - 1, w, w + 1, (1 << 31) - 1, (1 << 31) - w] + \
+                [rnd.randrange(1 << 31) for _ in range(20)]:
+            assert (n * m) >> k == n // w
+            assert n * m < (1 << 63)
