@@ -26,9 +26,10 @@ from .peaks import find_runs, find_events, EVENT_FIELDS
 from .pipeline import search
 from .coincidence import zero_dm_series, rfi_mask, binomial_tail
 from .baseline import baseline_remove
+from .cluster import cluster_events, CLUSTER_FIELDS
 
 __all__ = [
-    "baseline_remove",
+    "baseline_remove", "cluster_events", "CLUSTER_FIELDS",
     "zero_dm_series", "rfi_mask", "binomial_tail",
     "K_DM", "channel_freqs", "delay_table", "max_delay", "nearest_tie_distance",
     "unpack_2bit", "dedisperse", "brute_dedisperse", "prefix_sum", "boxcar",

@@ -431,3 +431,63 @@ def make_tiny(seed: int, nchans: int, nsamps: int, dm_list: Sequence[float],
     return Filterbank(f"tiny_{nchans}x{nsamps}", seed, nchans, nsamps, f_top, df,
                       tsamp, np.asarray(dm_list, dtype=np.float64), list(widths),
                       snr_thresh, packed, [])
+
+
+# ---------------------------------------------------------------------------
+# Event lists for the clustering stage.
+# ---------------------------------------------------------------------------
+
+EVENT_DTYPE = np.dtype([("width_idx", "<i4"), ("dm_idx", "<i4"), ("t_start", "<i8"),
+                        ("t_end", "<i8"), ("t_peak", "<i8"), ("b_peak", "<i4"),
+                        ("snr", "<f4")])
+
+
+def make_event_list(seed: int, ndm: int, nwidths: int, nout: int, nclumps: int = 20,
+                    nnoise: int = 200, dm_extent: int = 40, max_run: int = 6,
+                    snr_levels: int = 16) -> np.ndarray:
+    """A valid find_peaks-style event list (structured, EVENT_DTYPE): events in
+    (width_idx, dm_idx, t_start) order, runs of one series maximal (a gap of
+    at least one sample) and inside [0, nout).
+
+    Clumps imitate a dispersed pulse: a range of up to ``dm_extent`` trials
+    and a range of widths, with a run in each (trial, width) whose start
+    drifts by a sample or two per trial; noise events are isolated runs at
+    random places.  snr takes one of ``snr_levels`` values so that ties
+    occur."""
+    rng = np.random.default_rng(seed)
+    runs = {}
+
+    def add(w, d, s, e):
+        if 0 <= d < ndm and 0 <= w < nwidths:
+            s, e = max(0, s), min(nout - 1, e)
+            if s <= e:
+                runs.setdefault((w, d), []).append((s, e))
+
+    for _ in range(nclumps):
+        d0 = int(rng.integers(0, ndm))
+        nd = int(rng.integers(1, dm_extent + 1))
+        w0 = int(rng.integers(0, nwidths))
+        nw = int(rng.integers(1, min(4, nwidths) + 1))
+        t0 = int(rng.integers(0, nout))
+        drift = int(rng.integers(-2, 3))
+        for d in range(d0, d0 + nd):
+            if rng.random() < 0.1:
+                continue                               # a trial where the cut missed
+            for w in range(w0, w0 + nw):
+                s = t0 + drift * (d - d0) + int(rng.integers(-1, 2))
+                add(w, d, s, s + int(rng.integers(0, max_run)))
+    for _ in range(nnoise):
+        s = int(rng.integers(0, nout))
+        add(int(rng.integers(0, nwidths)), int(rng.integers(0, ndm)), s, s + int(rng.integers(0, 3)))
+    rows = []
+    for (w, d) in sorted(runs):
+        merged = []
+        for s, e in sorted(runs[(w, d)]):
+            if merged and s <= merged[-1][1] + 1:        # touching runs are one run
+                merged[-1][1] = max(merged[-1][1], e)
+            else:
+                merged.append([s, e])
+        for s, e in merged:
+            rows.append((w, d, s, e, int(rng.integers(s, e + 1)), int(rng.integers(1, 1 << 20)),
+                         np.float32(6.0 + rng.integers(0, snr_levels) * 0.5)))
+    return np.array(rows, dtype=EVENT_DTYPE)
