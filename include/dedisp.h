@@ -58,6 +58,22 @@ typedef struct {
     float snr;         /* (B - mean) / sigma at t_peak, population sigma        */
 } dedisp_event;
 
+/* One candidate: a cluster of events merged across DM trials and widths
+ * (dedisp_cluster_events).  72 bytes. */
+typedef struct {
+    int64_t first;     /* lowest event index in the cluster (its identity)      */
+    int64_t rep;       /* event of largest snr; ties to the lower index         */
+    int64_t t_lo;      /* first sample any member covers (min t_start)          */
+    int64_t t_hi;      /* last sample any member covers (max t_end + width - 1) */
+    int64_t t_peak;    /* t_peak of the representative                          */
+    int32_t n_members;
+    int32_t dm_lo, dm_hi;   /* DM-trial range of the members                    */
+    int32_t w_lo, w_hi;     /* width-index range of the members                 */
+    int32_t dm_idx;    /* of the representative                                 */
+    int32_t width_idx; /* of the representative                                 */
+    float snr;         /* of the representative                                 */
+} dedisp_cluster;
+
 typedef struct dedisp_plan_s* dedisp_plan;
 typedef struct triage_model_s* triage_model;
 
@@ -368,6 +384,45 @@ int64_t dedisp_now_ns(void);
  * (0 when not even one fits; at most 4096). */
 int64_t dedisp_percentile_ns(const int64_t* sorted, int64_t n, double q);
 int32_t dedisp_serve_admission(size_t budget, size_t resident, size_t slot_bytes);
+
+/* ------------------------------------------------------------------------
+ * Event clustering across DM trials and widths.  Section 2.3 gathers the
+ * above-cut samples of one series into events; one dispersed pulse crosses
+ * the cut in many neighbouring trials and widths and so gives many events.
+ * This merges them (friends of friends):
+ *   * event e covers samples [t_start, t_end + W - 1], W = widths[width_idx];
+ *   * a and b are friends when |dm_a - dm_b| <= dm_radius,
+ *     |width_idx_a - width_idx_b| <= width_radius, and
+ *     s_a <= e_b + time_tol and s_b <= e_a + time_tol (s, e: the spans);
+ *   * a cluster is a connected component of that relation.  Clusters are
+ *     listed in the order of their lowest-index member; the representative
+ *     is the member of largest snr, ties to the lower index (-0 equals +0).
+ *
+ * events: device, n_events records in the order and form find_peaks writes
+ *   (sorted by (width_idx, dm_idx, t_start); runs of one series disjoint and
+ *   increasing; 0 <= dm_idx < ndm, 0 <= width_idx < nwidths; t_start >= 0;
+ *   t_end >= t_start; snr not NaN).  Other input gives INVALID_ARG.
+ * widths: host, nwidths (1..32) boxcar widths, each in [1, 2^30].
+ * dm_radius in [0, 65535], width_radius in [0, 31], time_tol in [0, 2^40].
+ *   The cost per event grows with (2 dm_radius + 1)(2 width_radius + 1).
+ * clusters: device, capacity records; n_clusters: host, the number found.
+ *   If it exceeds capacity the first `capacity` clusters are written and
+ *   DEDISP_ERR_CAPACITY is returned.
+ * labels: device, n_events int32 (may be NULL): the cluster index of each
+ *   event (may exceed capacity).
+ * workspace: device, dedisp_cluster_workspace_bytes(n_events, ndm, nwidths)
+ *   bytes, 256-byte aligned; clobbered.  n_events <= 2^31 - 1.
+ * Deterministic: the output does not depend on thread timing.
+ * Synchronises `stream` (the count is read back).
+ * Errors: INVALID_ARG, CAPACITY, HIP.
+ * ------------------------------------------------------------------------ */
+size_t dedisp_cluster_workspace_bytes(int64_t n_events, int32_t ndm, int32_t nwidths);
+dedisp_status dedisp_cluster_events(const dedisp_event* events, int64_t n_events, int32_t ndm,
+                                    const int32_t* widths, int32_t nwidths, int32_t dm_radius,
+                                    int32_t width_radius, int64_t time_tol,
+                                    dedisp_cluster* clusters, int64_t capacity,
+                                    int64_t* n_clusters, int32_t* labels, void* workspace,
+                                    dedisp_stream stream);
 
 /* ------------------------------------------------------------------------
  * Multibeam coincidence RFI mask (section 2.1: interference is not localised,

@@ -79,9 +79,12 @@ def cluster_events(events, widths, dm_radius: int, width_radius: int, time_tol: 
     index = {int(comp[f]): c for c, f in enumerate(order)}
     labels = np.array([index[int(comp[k])] for k in range(n)], np.int64)
     s, e = spans(events, widths)
+    groups = [[] for _ in order]
+    for k in range(n):
+        groups[labels[k]].append(k)
     clusters = []
     for c, f in enumerate(order):
-        members = np.nonzero(labels == c)[0]
+        members = np.array(groups[c], np.int64)
         rep = int(members[0])
         for m in members[1:]:
             if ev["snr"][m] > ev["snr"][rep]:

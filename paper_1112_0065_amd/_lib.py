@@ -28,6 +28,11 @@ EVENT_DTYPE = np.dtype([("width_idx", "<i4"), ("dm_idx", "<i4"), ("t_start", "<i
                         ("t_end", "<i8"), ("t_peak", "<i8"), ("b_peak", "<i4"),
                         ("snr", "<f4")])
 assert EVENT_DTYPE.itemsize == 40
+CLUSTER_DTYPE = np.dtype([("first", "<i8"), ("rep", "<i8"), ("t_lo", "<i8"), ("t_hi", "<i8"),
+                          ("t_peak", "<i8"), ("n_members", "<i4"), ("dm_lo", "<i4"),
+                          ("dm_hi", "<i4"), ("w_lo", "<i4"), ("w_hi", "<i4"), ("dm_idx", "<i4"),
+                          ("width_idx", "<i4"), ("snr", "<f4")])
+assert CLUSTER_DTYPE.itemsize == 72
 
 
 class DedispError(RuntimeError):
@@ -97,6 +102,9 @@ def lib() -> C.CDLL:
         "dedisp_batch_destroy": (i32, [vp]),
         "dedisp_autotune": (i32, [vp, i64, i32, C.c_char_p, P(_Tile), P(i32)]),
         "dedisp_rfi_mask_workspace_bytes": (sz, [i32, i64]),
+        "dedisp_cluster_workspace_bytes": (sz, [i64, i32, i32]),
+        "dedisp_cluster_events": (i32, [vp, i64, i32, P(i32), i32, i32, i32, i64, vp, i64, P(i64),
+                                        vp, vp, vp]),
         "baseline_remove": (i32, [vp, i32, i32, i64, i32, i32, vp, i32, vp]),
         "dedisp_rfi_mask": (i32, [P(vp), i32, i32, i64, f32, i32, vp, P(i64), vp, vp]),
         "dedisp_rfi_mask_read_stats": (i32, [vp, i32, i64, P(i32), P(i64), vp]),
@@ -337,6 +345,40 @@ def events_from_buffer(buf, n: int) -> np.ndarray:
     if hasattr(raw, "cpu"):
         raw = raw.cpu().numpy()
     return np.frombuffer(np.asarray(raw, dtype=np.uint8).tobytes(), dtype=EVENT_DTYPE, count=n)
+
+
+# ---------------------------------------------------------------------------
+# Event clustering across DM and width
+# ---------------------------------------------------------------------------
+
+def dedisp_cluster_workspace_bytes(n_events: int, ndm: int, nwidths: int) -> int:
+    return int(lib().dedisp_cluster_workspace_bytes(int(n_events), int(ndm), int(nwidths)))
+
+
+def dedisp_cluster_events(events, n_events: int, ndm: int, widths, dm_radius: int,
+                          width_radius: int, time_tol: int, clusters, capacity: int, workspace,
+                          labels=None, stream=None) -> int:
+    """events: device buffer of n_events find_peaks records; clusters: device
+    buffer of capacity*72 bytes; labels: optional device int32 [n_events].
+    Returns the number of clusters (raises DedispError(CAPACITY) when it
+    exceeds capacity, after writing the first `capacity`)."""
+    n = C.c_int64()
+    st = lib().dedisp_cluster_events(_ptr(events), int(n_events), int(ndm), _i32arr(widths),
+                                     len(widths), int(dm_radius), int(width_radius),
+                                     int(time_tol), _ptr(clusters), int(capacity), C.byref(n),
+                                     _ptr(labels), _ptr(workspace), _stream(stream))
+    if st == ERR_CAPACITY:
+        raise DedispError(st, dedisp_last_error() + f" (n_clusters={n.value})")
+    _check(st)
+    return int(n.value)
+
+
+def clusters_from_buffer(buf, n: int) -> np.ndarray:
+    """Copy n cluster records from a device/host byte buffer to a structured array."""
+    raw = buf[: n * CLUSTER_DTYPE.itemsize]
+    if hasattr(raw, "cpu"):
+        raw = raw.cpu().numpy()
+    return np.frombuffer(np.asarray(raw, dtype=np.uint8).tobytes(), dtype=CLUSTER_DTYPE, count=n)
 
 
 # ---------------------------------------------------------------------------

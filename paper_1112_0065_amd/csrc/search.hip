@@ -978,6 +978,19 @@ PeaksWs peaks_ws(void* base, const PeaksLayout& lay) {
     return ws;
 }
 
+hipError_t launch_scan_u32(const uint32_t* counts, int64_t n, int64_t* offs, int64_t* chunk_tot,
+                           int64_t* total, hipStream_t s) {
+    const int nchunks = static_cast<int>((n + kScanChunk - 1) / kScanChunk);
+    hipLaunchKernelGGL(scan_chunks_kernel, dim3(nchunks), dim3(kThreads), 0, s, counts, n, offs,
+                       chunk_tot);
+    hipLaunchKernelGGL(scan_totals_kernel, dim3(1), dim3(64), 0, s, chunk_tot, nchunks, total);
+    hipLaunchKernelGGL(scan_add_kernel, dim3(static_cast<unsigned>((n + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, offs, n, chunk_tot);
+    return hipGetLastError();
+}
+
+int64_t scan_chunk_count(int64_t n) { return (n + kScanChunk - 1) / kScanChunk; }
+
 hipError_t launch_peaks_count(const void* in, int in_u16, int ndm, int64_t nout, const Widths& W,
                               const PeaksLayout& lay, const PeaksWs& ws, uint32_t kmant, int kexp2,
                               hipStream_t s) {
