@@ -234,6 +234,7 @@ def main():
                        "achieved_GBps": bl_bytes / (bl_ms * 1e-3) / 1e9,
                        "hbm_frac": bl_bytes / (bl_ms * 1e-3) / 8e12}
     del flat
+    rec["cluster"] = bench_cluster(evb, n_events, ndm, fb.widths)
     del out, ws, pws, evb, inp
     torch.cuda.empty_cache()
     if not args.no_multibeam:
@@ -361,6 +362,36 @@ def bench_serve(args):
             "batches": st["batches"], "mean_batch": st["mean_batch"], "max_batch": st["max_batch"],
             "slots": st["slots"], "busy_retries": busy, "wall_s": wall,
             "data": "4 fast-noise chunk payloads cycled over beams and sequence numbers"}
+
+
+def bench_cluster(evb, n_events, ndm, widths):
+    """Clustering of events across DM and width (friends of friends, DM
+    radius 2, width radius 1, no time slack): the survey beam's own events,
+    and a dense synthetic list of about a million events.  Each call includes
+    its host synchronisation (the cluster count is read back)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1112_0065_amd import _lib as L
+
+    def run(buf, n, nd, ws_w):
+        ws = torch.empty(max(L.dedisp_cluster_workspace_bytes(n, nd, len(ws_w)), 1),
+                         dtype=torch.uint8, device="cuda")
+        cb = torch.empty(max(n, 1) * 72, dtype=torch.uint8, device="cuda")
+        nc = L.dedisp_cluster_events(buf, n, nd, ws_w, 2, 1, 0, cb, n, ws)
+        reps = 20
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            L.dedisp_cluster_events(buf, n, nd, ws_w, 2, 1, 0, cb, n, ws)
+        dt = (time.perf_counter() - t0) / reps
+        return {"events": n, "clusters": nc, "ms": dt * 1e3, "events_per_s": n / dt}
+
+    res = {"survey_beam": run(evb, n_events, ndm, widths)}
+    ev = synth.make_event_list(77, 1200, 10, 1 << 22, nclumps=20000, nnoise=300000)
+    buf = torch.from_numpy(np.frombuffer(ev.tobytes(), np.uint8).copy()).to("cuda")
+    res["dense_synthetic"] = run(buf, len(ev), 1200, [1 << i for i in range(10)])
+    return res
 
 
 def bench_rfi_mask(args):

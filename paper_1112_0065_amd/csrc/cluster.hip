@@ -70,6 +70,20 @@ __device__ int find_root(int32_t* parent, int32_t x) {
     return x;
 }
 
+// An ancestor of x through wavefront-scope (cached) loads.  A cached parent
+// value may be old, but every value a parent slot ever held is an ancestor of
+// its node for good (trees only merge), so the result is always an ancestor
+// and equal results prove two nodes joined.  The walk ends because parents
+// decrease.
+__device__ int32_t find_cached(const int32_t* parent, int32_t x) {
+    int32_t p = __hip_atomic_load(parent + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    while (p != x) {
+        x = p;
+        p = __hip_atomic_load(parent + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+    return x;
+}
+
 __device__ void unite(int32_t* parent, int32_t a, int32_t b) {
     while (true) {
         a = find_root(parent, a);
@@ -106,12 +120,15 @@ __global__ void cluster_init_kernel(uint32_t* err) { *err = 0; }
 
 // Series starts: seg[k] = first event with series key >= k, k = w * ndm + d,
 // for k in [0, nwidths * ndm]; thread i (0 <= i <= n) fills the keys between
-// event i - 1's and its own.  Also checks the input order and fields.
+// event i - 1's and its own.  Also checks the input order and fields, and
+// starts every event as its own root.
 __global__ __launch_bounds__(kKThreads) void cluster_seg_kernel(ClusterParams P,
                                                                 int32_t* __restrict__ seg,
+                                                                int32_t* __restrict__ parent,
                                                                 uint32_t* __restrict__ err) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kKThreads + threadIdx.x;
     if (i > P.n) return;
+    if (i < P.n) parent[i] = static_cast<int32_t>(i);
     const int64_t K = static_cast<int64_t>(P.nwidths) * P.ndm;
     int64_t kprev = -1, kcur = K;
     bool bad = false;
@@ -139,47 +156,63 @@ __global__ __launch_bounds__(kKThreads) void cluster_seg_kernel(ClusterParams P,
     for (int64_t k = kprev + 1; k <= kcur; ++k) seg[k] = static_cast<int32_t>(i);
 }
 
-__global__ __launch_bounds__(kKThreads) void cluster_parent_init_kernel(int64_t n,
-                                                                        int32_t* __restrict__ parent) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kKThreads + threadIdx.x;
-    if (i < n) parent[i] = static_cast<int32_t>(i);
+// Neighbour series whose events can have larger indices than an event of
+// series (w, d): (w, d .. d + dm_radius) and (w + 1 .. w + width_radius,
+// d - dm_radius .. d + dm_radius) -- every series of smaller key holds only
+// smaller indices.
+__host__ __device__ inline int upper_series(int dm_radius, int width_radius) {
+    return dm_radius + 1 + width_radius * (2 * dm_radius + 1);
 }
 
-// Thread i unites event i with every friend of larger index.
+__device__ void link_one(const ClusterParams& P, const int32_t* __restrict__ seg, int32_t* parent,
+                         int64_t i, int sidx);
+
+// Thread q handles event q / S and its neighbour series q % S (S =
+// upper_series): it unites the event with every friend of larger index in
+// that series.  One series per thread keeps each thread's chain of dependent
+// loads short.
 __global__ __launch_bounds__(kKThreads) void cluster_link_kernel(ClusterParams P,
                                                                  const int32_t* __restrict__ seg,
                                                                  int32_t* parent) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kKThreads + threadIdx.x;
-    if (i >= P.n) return;
+    const int S = upper_series(P.dm_radius, P.width_radius);
+    const int64_t nq = P.n * S;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kKThreads;
+    for (int64_t q = static_cast<int64_t>(blockIdx.x) * kKThreads + threadIdx.x; q < nq; q += stride)
+        link_one(P, seg, parent, q / S, static_cast<int>(q % S));
+}
+
+__device__ void link_one(const ClusterParams& P, const int32_t* __restrict__ seg, int32_t* parent,
+                         int64_t i, int sidx) {
     const dedisp_event e = P.ev[i];
     if (!event_ok(e, P)) return;
+    int w = e.width_idx, d;
+    if (sidx <= P.dm_radius) {
+        d = e.dm_idx + sidx;
+    } else {
+        const int r = sidx - P.dm_radius - 1;
+        w += 1 + r / (2 * P.dm_radius + 1);
+        d = e.dm_idx - P.dm_radius + r % (2 * P.dm_radius + 1);
+    }
+    if (w >= P.nwidths || d < 0 || d >= P.ndm) return;
     const int64_t n = P.n;
-    const int64_t ki = static_cast<int64_t>(e.width_idx) * P.ndm + e.dm_idx;
-    const int64_t s_i = e.t_start;
-    const int64_t e_i = e.t_end + P.widths[e.width_idx] - 1;
-    const int w_lo = max(0, e.width_idx - P.width_radius);
-    const int w_hi = min(P.nwidths - 1, e.width_idx + P.width_radius);
-    const int d_lo = max(0, e.dm_idx - P.dm_radius);
-    const int d_hi = min(P.ndm - 1, e.dm_idx + P.dm_radius);
-    for (int w = w_lo; w <= w_hi; ++w) {
-        const int64_t want_end = s_i - P.time_tol - P.widths[w] + 1;   // friend: t_end >= this
-        const int64_t last_start = e_i + P.time_tol;                   // friend: t_start <= this
-        for (int d = d_lo; d <= d_hi; ++d) {
-            const int64_t k = static_cast<int64_t>(w) * P.ndm + d;
-            if (k < ki) continue;                   // those events all have smaller indices
-            int64_t a = min<int64_t>(max<int64_t>(seg[k], 0), n);
-            const int64_t b = min<int64_t>(max<int64_t>(seg[k + 1], a), n);
-            if (k == ki) a = max(a, i + 1);
-            // first index in [a, b) with t_end >= want_end
-            int64_t lo = a, hi = b;
-            while (lo < hi) {
-                const int64_t mid = (lo + hi) >> 1;
-                if (P.ev[mid].t_end < want_end) lo = mid + 1;
-                else hi = mid;
-            }
-            for (int64_t j = lo; j < b && P.ev[j].t_start <= last_start; ++j)
-                unite(parent, static_cast<int32_t>(i), static_cast<int32_t>(j));
-        }
+    const int64_t k = static_cast<int64_t>(w) * P.ndm + d;
+    int64_t a = min<int64_t>(max<int64_t>(seg[k], 0), n);
+    const int64_t b = min<int64_t>(max<int64_t>(seg[k + 1], a), n);
+    if (sidx == 0) a = max(a, i + 1);            // own series: later runs only
+    const int64_t want_end = e.t_start - P.time_tol - P.widths[w] + 1;   // friend: t_end >= this
+    const int64_t last_start = e.t_end + P.widths[e.width_idx] - 1 + P.time_tol;
+    int64_t lo = a, hi = b;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (P.ev[mid].t_end < want_end) lo = mid + 1;
+        else hi = mid;
+    }
+    for (int64_t j = lo; j < b && P.ev[j].t_start <= last_start; ++j) {
+        // most friends are already joined: a common ancestor seen through
+        // ordinary cached loads settles that without the coherent union
+        const int32_t ra = find_cached(parent, static_cast<int32_t>(i));
+        const int32_t rb = find_cached(parent, static_cast<int32_t>(j));
+        if (ra != rb) unite(parent, ra, rb);
     }
 }
 
@@ -209,27 +242,71 @@ __global__ __launch_bounds__(kKThreads) void cluster_finish_kernel(
     key[i] = 0;
 }
 
+// Events per block of the accumulation and its LDS table (load <= 1/2).
+constexpr int kAccEvents = 512;
+constexpr int kAccSlots = 1024;
+
+// Member count, bounds and representative of every cluster.  A block first
+// merges its events per root in an LDS hash table (roots are event indices;
+// linear probing), then adds each distinct root once to the global slots:
+// one global atomic per field and root per block instead of per event, which
+// matters when large clusters would serialise on their root's slot.
 __global__ __launch_bounds__(kKThreads) void cluster_accumulate_kernel(
     ClusterParams P, const int32_t* __restrict__ parent, const int64_t* __restrict__ offs,
     uint32_t* cnt, int32_t* dmlo, int32_t* dmhi, int32_t* wlo, int32_t* whi, uint64_t* tlo,
     uint64_t* thi, uint64_t* key, int32_t* __restrict__ labels) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kKThreads + threadIdx.x;
-    if (i >= P.n) return;
-    const dedisp_event e = P.ev[i];
-    const int32_t r = parent[i];
-    if (labels) labels[i] = static_cast<int32_t>(offs[r]);
-    if (!event_ok(e, P)) return;
-    atomicAdd(cnt + r, 1u);
-    atomicMin(dmlo + r, e.dm_idx);
-    atomicMax(dmhi + r, e.dm_idx);
-    atomicMin(wlo + r, e.width_idx);
-    atomicMax(whi + r, e.width_idx);
-    atomicMin(reinterpret_cast<unsigned long long*>(tlo + r),
-              static_cast<unsigned long long>(e.t_start));
-    atomicMax(reinterpret_cast<unsigned long long*>(thi + r),
-              static_cast<unsigned long long>(e.t_end + P.widths[e.width_idx] - 1));
-    atomicMax(reinterpret_cast<unsigned long long*>(key + r),
-              static_cast<unsigned long long>(rep_key(e.snr, i)));
+    __shared__ int32_t s_root[kAccSlots];
+    __shared__ uint32_t s_cnt[kAccSlots];
+    __shared__ int32_t s_dmlo[kAccSlots], s_dmhi[kAccSlots], s_wlo[kAccSlots], s_whi[kAccSlots];
+    __shared__ unsigned long long s_tlo[kAccSlots], s_thi[kAccSlots], s_key[kAccSlots];
+    for (int h = threadIdx.x; h < kAccSlots; h += kKThreads) {
+        s_root[h] = -1;
+        s_cnt[h] = 0;
+        s_dmlo[h] = INT_MAX;
+        s_dmhi[h] = INT_MIN;
+        s_wlo[h] = INT_MAX;
+        s_whi[h] = INT_MIN;
+        s_tlo[h] = ~0ull;
+        s_thi[h] = 0;
+        s_key[h] = 0;
+    }
+    __syncthreads();
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kAccEvents;
+    for (int k = threadIdx.x; k < kAccEvents; k += kKThreads) {
+        const int64_t i = i0 + k;
+        if (i >= P.n) break;
+        const int32_t r = parent[i];
+        if (labels) labels[i] = static_cast<int32_t>(offs[r]);
+        const dedisp_event e = P.ev[i];
+        if (!event_ok(e, P)) continue;
+        uint32_t h = (static_cast<uint32_t>(r) * 2654435761u) >> 22;   // 10 bits
+        while (true) {
+            const int32_t old = atomicCAS(s_root + h, -1, r);
+            if (old == -1 || old == r) break;
+            h = (h + 1) & (kAccSlots - 1);
+        }
+        atomicAdd(s_cnt + h, 1u);
+        atomicMin(s_dmlo + h, e.dm_idx);
+        atomicMax(s_dmhi + h, e.dm_idx);
+        atomicMin(s_wlo + h, e.width_idx);
+        atomicMax(s_whi + h, e.width_idx);
+        atomicMin(s_tlo + h, static_cast<unsigned long long>(e.t_start));
+        atomicMax(s_thi + h, static_cast<unsigned long long>(e.t_end + P.widths[e.width_idx] - 1));
+        atomicMax(s_key + h, static_cast<unsigned long long>(rep_key(e.snr, i)));
+    }
+    __syncthreads();
+    for (int h = threadIdx.x; h < kAccSlots; h += kKThreads) {
+        const int32_t r = s_root[h];
+        if (r < 0 || s_cnt[h] == 0) continue;
+        atomicAdd(cnt + r, s_cnt[h]);
+        atomicMin(dmlo + r, s_dmlo[h]);
+        atomicMax(dmhi + r, s_dmhi[h]);
+        atomicMin(wlo + r, s_wlo[h]);
+        atomicMax(whi + r, s_whi[h]);
+        atomicMin(reinterpret_cast<unsigned long long*>(tlo + r), s_tlo[h]);
+        atomicMax(reinterpret_cast<unsigned long long*>(thi + r), s_thi[h]);
+        atomicMax(reinterpret_cast<unsigned long long*>(key + r), s_key[h]);
+    }
 }
 
 __global__ __launch_bounds__(kKThreads) void cluster_write_kernel(
@@ -243,7 +320,8 @@ __global__ __launch_bounds__(kKThreads) void cluster_write_kernel(
     if (i >= P.n || !flag[i]) return;
     const int64_t c = offs[i];
     if (c >= capacity) return;
-    const int64_t rep = 0xFFFFFFFFll - static_cast<int64_t>(key[i] & 0xFFFFFFFFull);
+    // key 0 only when no valid member reached the slot (rejected input): stay in bounds
+    const int64_t rep = key[i] ? 0xFFFFFFFFll - static_cast<int64_t>(key[i] & 0xFFFFFFFFull) : i;
     const dedisp_event e = P.ev[rep];
     dedisp_cluster o;
     o.first = i;
@@ -291,8 +369,8 @@ ClusterLayout cluster_layout(int64_t n, int32_t ndm, int32_t nwidths) {
     L.o_key = take(un * 8);
     L.o_offs = take(un * 8);
     L.o_chunk = take(static_cast<size_t>(dd::scan_chunk_count(static_cast<int64_t>(un))) * 8);
-    L.o_total = take(8);
-    L.o_err = take(8);
+    L.o_total = take(16);   // int64 count, then the uint32 error flag
+    L.o_err = L.o_total + 8;
     L.bytes = o;
     return L;
 }
@@ -344,14 +422,18 @@ hipError_t launch_cluster(const dedisp_event* ev, int64_t n, int32_t ndm, const 
     const dim3 g_n(static_cast<unsigned>((n + kKThreads - 1) / kKThreads));
     const dim3 g_n1(static_cast<unsigned>((n + 1 + kKThreads - 1) / kKThreads));
     hipLaunchKernelGGL(cluster_init_kernel, dim3(1), dim3(1), 0, s, *err);
-    hipLaunchKernelGGL(cluster_seg_kernel, g_n1, blk, 0, s, P, seg, *err);
-    hipLaunchKernelGGL(cluster_parent_init_kernel, g_n, blk, 0, s, n, parent);
-    hipLaunchKernelGGL(cluster_link_kernel, g_n, blk, 0, s, P, seg, parent);
+    hipLaunchKernelGGL(cluster_seg_kernel, g_n1, blk, 0, s, P, seg, parent, *err);
+    const int64_t nq = n * upper_series(dm_radius, width_radius);
+    const int64_t link_blocks = std::min<int64_t>((nq + kKThreads - 1) / kKThreads, int64_t(1) << 20);
+    hipLaunchKernelGGL(cluster_link_kernel, dim3(static_cast<unsigned>(link_blocks)), blk, 0, s, P,
+                       seg, parent);
     hipLaunchKernelGGL(cluster_finish_kernel, g_n, blk, 0, s, n, parent, flag, cnt, dmlo, dmhi,
                        wlo, whi, tlo, thi, key);
     hipError_t e = launch_scan_u32(flag, n, offs, chunk, *total, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(cluster_accumulate_kernel, g_n, blk, 0, s, P, parent, offs, cnt, dmlo, dmhi,
+    hipLaunchKernelGGL(cluster_accumulate_kernel,
+                       dim3(static_cast<unsigned>((n + kAccEvents - 1) / kAccEvents)), blk, 0, s,
+                       P, parent, offs, cnt, dmlo, dmhi,
                        wlo, whi, tlo, thi, key, labels);
     if (capacity > 0)
         hipLaunchKernelGGL(cluster_write_kernel, g_n, blk, 0, s, P, flag, offs, cnt, dmlo, dmhi, wlo,
@@ -403,11 +485,12 @@ extern "C" dedisp_status dedisp_cluster_events(const dedisp_event* events, int64
     DD_HIP(dd::launch_cluster(events, n_events, ndm, widths, nwidths, dm_radius, width_radius,
                               time_tol, clusters, capacity, labels, workspace, &d_total, &d_err,
                               stream));
-    int64_t total = 0;
-    uint32_t err = 0;
-    DD_HIP(hipMemcpyAsync(&total, d_total, sizeof total, hipMemcpyDeviceToHost, stream));
-    DD_HIP(hipMemcpyAsync(&err, d_err, sizeof err, hipMemcpyDeviceToHost, stream));
+    int64_t back[2] = {0, 0};   // count, error flag (adjacent in the workspace)
+    DD_HIP(hipMemcpyAsync(back, d_total, sizeof back, hipMemcpyDeviceToHost, stream));
     DD_HIP(hipStreamSynchronize(stream));
+    const int64_t total = back[0];
+    const uint32_t err = static_cast<uint32_t>(back[1]);
+    (void)d_err;
     if (err)
         return fail(DEDISP_ERR_INVALID_ARG,
                     "events are not in find_peaks order or have fields out of range");

@@ -558,16 +558,34 @@ __global__ __launch_bounds__(kThreads) void scan_chunks_kernel(const uint32_t* _
     if (threadIdx.x == 0) chunk_tot[blockIdx.x] = carry;
 }
 
-__global__ void scan_totals_kernel(int64_t* __restrict__ chunk_tot, int nchunks,
-                                   int64_t* __restrict__ total) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int64_t run = 0;
-    for (int i = 0; i < nchunks; ++i) {
-        const int64_t v = chunk_tot[i];
-        chunk_tot[i] = run;
-        run += v;
+// Exclusive scan of the chunk totals in place (one block; 64-bit sums).
+__global__ __launch_bounds__(kThreads) void scan_totals_kernel(int64_t* __restrict__ chunk_tot,
+                                                               int nchunks,
+                                                               int64_t* __restrict__ total) {
+    __shared__ int64_t wave_tot[kThreads / 64];
+    __shared__ int64_t carry;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nchunks; base += kThreads) {
+        const int i = base + static_cast<int>(threadIdx.x);
+        const int64_t v = i < nchunks ? chunk_tot[i] : 0;
+        int64_t x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wave_tot[wave] = x;
+        __syncthreads();
+        int64_t before = carry;
+        for (int w = 0; w < wave; ++w) before += wave_tot[w];
+        if (i < nchunks) chunk_tot[i] = before + x - v;
+        __syncthreads();
+        if (threadIdx.x == kThreads - 1) carry = before + x;
+        __syncthreads();
     }
-    *total = run;
+    if (threadIdx.x == 0) *total = carry;
 }
 
 __global__ __launch_bounds__(kThreads) void scan_add_kernel(int64_t* __restrict__ offs, int64_t n,
@@ -983,7 +1001,7 @@ hipError_t launch_scan_u32(const uint32_t* counts, int64_t n, int64_t* offs, int
     const int nchunks = static_cast<int>((n + kScanChunk - 1) / kScanChunk);
     hipLaunchKernelGGL(scan_chunks_kernel, dim3(nchunks), dim3(kThreads), 0, s, counts, n, offs,
                        chunk_tot);
-    hipLaunchKernelGGL(scan_totals_kernel, dim3(1), dim3(64), 0, s, chunk_tot, nchunks, total);
+    hipLaunchKernelGGL(scan_totals_kernel, dim3(1), dim3(kThreads), 0, s, chunk_tot, nchunks, total);
     hipLaunchKernelGGL(scan_add_kernel, dim3(static_cast<unsigned>((n + kThreads - 1) / kThreads)),
                        dim3(kThreads), 0, s, offs, n, chunk_tot);
     return hipGetLastError();
@@ -1023,7 +1041,7 @@ hipError_t launch_peaks_count(const void* in, int in_u16, int ndm, int64_t nout,
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(scan_chunks_kernel, dim3(lay.nchunks), dim3(kThreads), 0, s, ws.counts,
                        lay.ncounts, ws.offs, ws.chunk_tot);
-    hipLaunchKernelGGL(scan_totals_kernel, dim3(1), dim3(64), 0, s, ws.chunk_tot, lay.nchunks, ws.total);
+    hipLaunchKernelGGL(scan_totals_kernel, dim3(1), dim3(kThreads), 0, s, ws.chunk_tot, lay.nchunks, ws.total);
     hipLaunchKernelGGL(scan_add_kernel, dim3(static_cast<unsigned>((lay.ncounts + kThreads - 1) / kThreads)),
                        dim3(kThreads), 0, s, ws.offs, lay.ncounts, ws.chunk_tot);
     return hipGetLastError();
