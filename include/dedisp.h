@@ -74,6 +74,17 @@ typedef struct {
     float snr;         /* of the representative                                 */
 } dedisp_cluster;
 
+/* A window of raw input samples to dump from a baseband buffer
+ * (dedisp_trigger_windows).  32 bytes. */
+typedef struct {
+    int64_t start;       /* first raw sample                                    */
+    int64_t end;         /* one past the last raw sample                        */
+    float snr;           /* largest cluster snr inside the window               */
+    int32_t cluster;     /* index (into the clusters given) of that cluster     */
+    int32_t n_clusters;  /* clusters merged into the window                     */
+    int32_t reserved;
+} dedisp_trigger;
+
 typedef struct dedisp_plan_s* dedisp_plan;
 typedef struct triage_model_s* triage_model;
 
@@ -423,6 +434,41 @@ dedisp_status dedisp_cluster_events(const dedisp_event* events, int64_t n_events
                                     dedisp_cluster* clusters, int64_t capacity,
                                     int64_t* n_clusters, int32_t* labels, void* workspace,
                                     dedisp_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Candidate export and baseband-dump triggers (host code).  The introduction
+ * motivates real-time processing by immediate follow-up of events and by
+ * dumps of the full-resolution baseband data, held briefly in a buffer and
+ * written out when an event merits it.
+ *
+ * dedisp_write_candidates: one text line per cluster (host array), after a
+ *   '#' header naming the columns: snr (%.9g), t_peak + t_offset,
+ *   (t_peak + t_offset) * tsamp, dm_list[dm_idx], dm_idx, widths[width_idx],
+ *   width_idx, n_members, t_lo + t_offset, t_hi + t_offset, dm_lo, dm_hi, beam.
+ *   Time and DM print with %.17g (they read back exactly).  Overwrites path.
+ *   Errors: INVALID_ARG (NULL, bad sizes, an index outside the lists, I/O).
+ *
+ * dedisp_trigger_windows: for every cluster with snr >= snr_min and
+ *   n_members >= min_members, the raw samples that fed its dedispersed span
+ *   [t_lo, t_hi] in any channel at any trial of [dm_lo, dm_hi]:
+ *     [t_lo + min delay - pad, t_hi + max delay + pad], both ends inclusive,
+ *   min/max over those trials and all channels of delays (host, [ndm][nchans],
+ *   as dedisp_plan_copy_delays gives), clipped to [0, nsamps).  Windows that
+ *   overlap or touch are merged; the result is sorted by start and written to
+ *   out (host, capacity records).  Samples are relative to the first input
+ *   sample of the searched block.  *n_out receives the number of windows; if
+ *   it exceeds capacity the first `capacity` are written and CAPACITY is
+ *   returned.  Errors: INVALID_ARG, CAPACITY.
+ * ------------------------------------------------------------------------ */
+dedisp_status dedisp_write_candidates(const char* path, const dedisp_cluster* clusters, int64_t n,
+                                      const double* dm_list, int32_t ndm, const int32_t* widths,
+                                      int32_t nwidths, double tsamp, int64_t t_offset,
+                                      int32_t beam);
+dedisp_status dedisp_trigger_windows(const dedisp_cluster* clusters, int64_t n,
+                                     const int32_t* delays, int32_t ndm, int32_t nchans,
+                                     float snr_min, int32_t min_members, int64_t pad,
+                                     int64_t nsamps, dedisp_trigger* out, int64_t capacity,
+                                     int64_t* n_out);
 
 /* ------------------------------------------------------------------------
  * Multibeam coincidence RFI mask (section 2.1: interference is not localised,

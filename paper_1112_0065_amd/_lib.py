@@ -33,6 +33,9 @@ CLUSTER_DTYPE = np.dtype([("first", "<i8"), ("rep", "<i8"), ("t_lo", "<i8"), ("t
                           ("dm_hi", "<i4"), ("w_lo", "<i4"), ("w_hi", "<i4"), ("dm_idx", "<i4"),
                           ("width_idx", "<i4"), ("snr", "<f4")])
 assert CLUSTER_DTYPE.itemsize == 72
+TRIGGER_DTYPE = np.dtype([("start", "<i8"), ("end", "<i8"), ("snr", "<f4"), ("cluster", "<i4"),
+                          ("n_clusters", "<i4"), ("reserved", "<i4")])
+assert TRIGGER_DTYPE.itemsize == 32
 
 
 class DedispError(RuntimeError):
@@ -103,6 +106,10 @@ def lib() -> C.CDLL:
         "dedisp_autotune": (i32, [vp, i64, i32, C.c_char_p, P(_Tile), P(i32)]),
         "dedisp_rfi_mask_workspace_bytes": (sz, [i32, i64]),
         "dedisp_cluster_workspace_bytes": (sz, [i64, i32, i32]),
+        "dedisp_write_candidates": (i32, [C.c_char_p, vp, i64, P(f64), i32, P(i32), i32, f64, i64,
+                                          i32]),
+        "dedisp_trigger_windows": (i32, [vp, i64, P(i32), i32, i32, f32, i32, i64, i64, vp, i64,
+                                         P(i64)]),
         "dedisp_cluster_events": (i32, [vp, i64, i32, P(i32), i32, i32, i32, i64, vp, i64, P(i64),
                                         vp, vp, vp]),
         "baseline_remove": (i32, [vp, i32, i32, i64, i32, i32, vp, i32, vp]),
@@ -371,6 +378,37 @@ def dedisp_cluster_events(events, n_events: int, ndm: int, widths, dm_radius: in
         raise DedispError(st, dedisp_last_error() + f" (n_clusters={n.value})")
     _check(st)
     return int(n.value)
+
+
+def dedisp_write_candidates(path: str, clusters: np.ndarray, dm_list, widths, tsamp: float,
+                            t_offset: int = 0, beam: int = 0):
+    """Write the cluster records (host structured array, CLUSTER_DTYPE) as a
+    text candidate list."""
+    c = np.ascontiguousarray(clusters, dtype=CLUSTER_DTYPE)
+    dm = np.ascontiguousarray(dm_list, dtype=np.float64)
+    _check(lib().dedisp_write_candidates(str(path).encode(), c.ctypes.data if len(c) else None,
+                                         len(c), dm.ctypes.data_as(C.POINTER(C.c_double)), len(dm),
+                                         _i32arr(widths), len(widths), float(tsamp), int(t_offset),
+                                         int(beam)))
+
+
+def dedisp_trigger_windows(clusters: np.ndarray, delays: np.ndarray, snr_min: float,
+                           min_members: int, pad: int, nsamps: int,
+                           capacity: Optional[int] = None) -> np.ndarray:
+    """Baseband-dump windows of the clusters (host arrays; delays [ndm][nchans])."""
+    c = np.ascontiguousarray(clusters, dtype=CLUSTER_DTYPE)
+    d = np.ascontiguousarray(delays, dtype=np.int32)
+    cap = len(c) if capacity is None else int(capacity)
+    out = np.zeros(max(cap, 1), dtype=TRIGGER_DTYPE)
+    n = C.c_int64()
+    st = lib().dedisp_trigger_windows(c.ctypes.data if len(c) else None, len(c),
+                                      d.ctypes.data_as(C.POINTER(C.c_int32)), d.shape[0],
+                                      d.shape[1], float(snr_min), int(min_members), int(pad),
+                                      int(nsamps), out.ctypes.data, cap, C.byref(n))
+    if st == ERR_CAPACITY:
+        raise DedispError(st, dedisp_last_error() + f" (n_windows={n.value})")
+    _check(st)
+    return out[: n.value].copy()
 
 
 def clusters_from_buffer(buf, n: int) -> np.ndarray:
