@@ -350,7 +350,8 @@ enum {
     DEDISP_CHUNK_GAP = 1,       /* the chunk does not follow the previous one */
     DEDISP_CHUNK_LATE = 2,      /* result later than the chunk duration       */
     DEDISP_CHUNK_FALLBACK = 4,  /* no triage scores (no or invalid model)     */
-    DEDISP_CHUNK_OVERFLOW = 8   /* more than 65536 events: first 65536 kept   */
+    DEDISP_CHUNK_OVERFLOW = 8,  /* more than 65536 events: first 65536 kept   */
+    DEDISP_CHUNK_CLUSTERED = 16 /* clusters of the kept events are attached   */
 };
 
 typedef struct {
@@ -363,6 +364,9 @@ typedef struct {
     const float* scores;   /* host, triage score per event, or NULL                        */
     int64_t arrival_ns, done_ns;
     int32_t flags;
+    int64_t n_clusters;    /* clusters of the kept events (CLUSTERED), else 0           */
+    const dedisp_cluster* clusters;  /* host, n_clusters records, t relative to t_abs0,
+                                        rep/first index the chunk's events, or NULL      */
 } dedisp_chunk_result;
 
 typedef struct {
@@ -386,6 +390,15 @@ dedisp_status dedisp_serve_submit(dedisp_server s, int32_t beam, int64_t seq,
 dedisp_status dedisp_serve_poll(dedisp_server s, dedisp_chunk_result* out, int32_t cap,
                                 int32_t* n_out, int32_t timeout_ms);
 dedisp_status dedisp_serve_stats(dedisp_server s, dedisp_serve_stats_t* stats);
+/* Cluster every chunk's kept events across DM and width (the rule of
+ * dedisp_cluster_events, same parameter ranges) before its result is
+ * returned; results then carry CLUSTERED and their clusters.  Call before the
+ * first submit (else BUSY).  Allocates, per chunk slot, a cluster workspace
+ * and a 65536-record cluster buffer beyond the HBM budget given at create
+ * (about 9 MB per slot at 1200 trials).  Errors: INVALID_ARG, BUSY,
+ * OUT_OF_MEMORY. */
+dedisp_status dedisp_serve_set_clustering(dedisp_server s, int32_t dm_radius,
+                                          int32_t width_radius, int64_t time_tol);
 dedisp_status dedisp_serve_destroy(dedisp_server s);
 /* Current time of the clock arrival_ns refers to. */
 int64_t dedisp_now_ns(void);

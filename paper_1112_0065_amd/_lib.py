@@ -52,7 +52,8 @@ class _ChunkResult(C.Structure):
     _fields_ = [("beam", C.c_int32), ("seq", C.c_int64), ("t_abs0", C.c_int64),
                 ("n_bx", C.c_int64), ("n_events", C.c_int64), ("events", C.c_void_p),
                 ("scores", C.POINTER(C.c_float)), ("arrival_ns", C.c_int64),
-                ("done_ns", C.c_int64), ("flags", C.c_int32)]
+                ("done_ns", C.c_int64), ("flags", C.c_int32), ("n_clusters", C.c_int64),
+                ("clusters", C.c_void_p)]
 
 
 class _ServeStats(C.Structure):
@@ -62,7 +63,7 @@ class _ServeStats(C.Structure):
                 ("max_batch", C.c_int64), ("mean_batch", C.c_double), ("slots", C.c_int32)]
 
 
-CHUNK_GAP, CHUNK_LATE, CHUNK_FALLBACK, CHUNK_OVERFLOW = 1, 2, 4, 8
+CHUNK_GAP, CHUNK_LATE, CHUNK_FALLBACK, CHUNK_OVERFLOW, CHUNK_CLUSTERED = 1, 2, 4, 8, 16
 
 _lib = None
 
@@ -121,6 +122,7 @@ def lib() -> C.CDLL:
         "dedisp_serve_poll": (i32, [vp, P(_ChunkResult), i32, P(i32), i32]),
         "dedisp_serve_stats": (i32, [vp, P(_ServeStats)]),
         "dedisp_serve_destroy": (i32, [vp]),
+        "dedisp_serve_set_clustering": (i32, [vp, i32, i32, i64]),
         "dedisp_now_ns": (i64, []),
         "dedisp_percentile_ns": (i64, [P(i64), i64, f64]),
         "dedisp_serve_admission": (i32, [sz, sz, sz]),
@@ -577,10 +579,23 @@ def dedisp_serve_poll(server: Server, cap: int = 64, timeout_ms: int = 0):
         scores = None
         if m and r.scores:
             scores = np.ctypeslib.as_array(r.scores, shape=(m,)).copy()
+        clusters = None
+        if r.flags & CHUNK_CLUSTERED:
+            clusters = np.empty(0, dtype=CLUSTER_DTYPE)
+            if r.n_clusters and r.clusters:
+                raw = C.string_at(r.clusters, r.n_clusters * CLUSTER_DTYPE.itemsize)
+                clusters = np.frombuffer(raw, dtype=CLUSTER_DTYPE).copy()
         out.append(dict(beam=r.beam, seq=r.seq, t_abs0=r.t_abs0, n_bx=r.n_bx,
                         n_events=r.n_events, events=ev, scores=scores,
-                        arrival_ns=r.arrival_ns, done_ns=r.done_ns, flags=r.flags))
+                        arrival_ns=r.arrival_ns, done_ns=r.done_ns, flags=r.flags,
+                        clusters=clusters))
     return out
+
+
+def dedisp_serve_set_clustering(server: Server, dm_radius: int, width_radius: int, time_tol: int):
+    """Cluster every chunk's events before its result is returned."""
+    _check(lib().dedisp_serve_set_clustering(server.handle, int(dm_radius), int(width_radius),
+                                             int(time_tol)))
 
 
 def dedisp_serve_stats(server: Server) -> dict:

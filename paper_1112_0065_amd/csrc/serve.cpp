@@ -53,6 +53,8 @@ struct Slot {
     void* out = nullptr;          // uint16 series
     void* pk_ws = nullptr;        // find_peaks workspace
     dedisp_event* d_events = nullptr;
+    void* cl_ws = nullptr;              // clustering workspace (when enabled)
+    dedisp_cluster* d_clusters = nullptr;
     bool busy = false;
 };
 
@@ -79,6 +81,7 @@ struct Result {
     dedisp_chunk_result r;
     std::vector<dedisp_event> events;
     std::vector<float> scores;
+    std::vector<dedisp_cluster> clusters;
 };
 
 }  // namespace
@@ -102,6 +105,11 @@ struct dedisp_server_s {
     triage_model model = nullptr;
     float triage_thresh = 0.5f;
     double deadline_ns = 0;
+    int64_t ndm_max = 0;
+    // clustering of each chunk's events (dedisp_serve_set_clustering)
+    bool cluster_on = false;
+    int32_t cl_dm_radius = 0, cl_width_radius = 0;
+    int64_t cl_time_tol = 0;
 
     // device
     std::vector<uint8_t*> overlap;       // per beam, H_b samples of packed input
@@ -272,6 +280,35 @@ void completer(dedisp_server_s* s) {
             if (e == hipSuccess) e = hipStreamSynchronize(s->done_s);
             int32_t flags = j.flags;
             if (n > s->capacity) flags |= DEDISP_CHUNK_OVERFLOW;
+            if (e == hipSuccess && s->cluster_on) {
+                const Slot& sl = s->slots[j.slot];
+                int64_t nc = 0;
+                if (m > 0) {
+                    int64_t* d_total = nullptr;
+                    uint32_t* d_err = nullptr;
+                    int64_t back[2] = {0, 0};
+                    e = dd::launch_cluster(sl.d_events, m, s->plans[j.beam]->ndm, s->W.w, s->W.n,
+                                           s->cl_dm_radius, s->cl_width_radius, s->cl_time_tol,
+                                           sl.d_clusters, s->capacity, nullptr, sl.cl_ws, &d_total,
+                                           &d_err, s->done_s);
+                    if (e == hipSuccess)
+                        e = hipMemcpyAsync(back, d_total, sizeof back, hipMemcpyDeviceToHost, s->done_s);
+                    if (e == hipSuccess) e = hipStreamSynchronize(s->done_s);
+                    // find_peaks output always passes the input checks; a
+                    // failed check leaves the chunk unclustered
+                    nc = static_cast<uint32_t>(back[1]) ? -1 : std::min(back[0], s->capacity);
+                    if (e == hipSuccess && nc > 0) {
+                        r.clusters.resize(static_cast<size_t>(nc));
+                        e = hipMemcpyAsync(r.clusters.data(), sl.d_clusters, nc * sizeof(dedisp_cluster),
+                                           hipMemcpyDeviceToHost, s->done_s);
+                        if (e == hipSuccess) e = hipStreamSynchronize(s->done_s);
+                    }
+                }
+                if (nc >= 0) {
+                    flags |= DEDISP_CHUNK_CLUSTERED;
+                    r.r.n_clusters = nc;
+                }
+            }
             if (e == hipSuccess && s->model) {
                 const dedisp_plan_s* p = s->plans[j.beam];
                 const int64_t nout = j.nsamps - p->max_delay;
@@ -325,6 +362,8 @@ void free_server(dedisp_server_s* s) {
         if (sl.out) (void)hipFree(sl.out);
         if (sl.pk_ws) (void)hipFree(sl.pk_ws);
         if (sl.d_events) (void)hipFree(sl.d_events);
+        if (sl.cl_ws) (void)hipFree(sl.cl_ws);
+        if (sl.d_clusters) (void)hipFree(sl.d_clusters);
     }
     for (int i = 0; i < dedisp_server_s::kRing; ++i) {
         if (s->h_beams[i]) (void)hipHostFree(s->h_beams[i]);
@@ -459,6 +498,7 @@ extern "C" dedisp_status dedisp_serve_create(const dedisp_plan* plans, int32_t n
     const int64_t win = s->H + s->C;
     int64_t ndm_max = 0;
     for (int b = 0; b < nbeams; ++b) ndm_max = std::max<int64_t>(ndm_max, plans[b]->ndm);
+    s->ndm_max = ndm_max;
     s->overlap.assign(nbeams, nullptr);
     for (int b = 0; b < nbeams && e == hipSuccess; ++b)
         e = hipMalloc(&s->overlap[b], static_cast<size_t>(s->Hb[b] * nchans / 4));
@@ -557,6 +597,7 @@ extern "C" dedisp_status dedisp_serve_poll(dedisp_server s, dedisp_chunk_result*
         Result& r = s->last_polled[i];
         r.r.events = r.events.empty() ? nullptr : r.events.data();
         r.r.scores = r.scores.empty() ? nullptr : r.scores.data();
+        r.r.clusters = r.clusters.empty() ? nullptr : r.clusters.data();
         out[i] = r.r;
     }
     *n_out = static_cast<int32_t>(s->last_polled.size());
@@ -579,6 +620,43 @@ extern "C" dedisp_status dedisp_serve_stats(dedisp_server s, dedisp_serve_stats_
     st->mean_batch = s->batches ? static_cast<double>(s->batched_chunks) / s->batches : 0.0;
     st->slots = static_cast<int32_t>(s->slots.size());
     st->deadline_ns = static_cast<int64_t>(s->deadline_ns);
+    return DEDISP_OK;
+}
+
+extern "C" dedisp_status dedisp_serve_set_clustering(dedisp_server s, int32_t dm_radius,
+                                                     int32_t width_radius, int64_t time_tol) {
+    if (!s) return fail(DEDISP_ERR_INVALID_ARG, "server is NULL");
+    if (dm_radius < 0 || dm_radius > 65535 || width_radius < 0 || width_radius > 31 ||
+        time_tol < 0 || time_tol > (int64_t(1) << 40))
+        return fail(DEDISP_ERR_INVALID_ARG, "radius or tolerance out of range");
+    std::lock_guard<std::mutex> g(s->mu);
+    for (int64_t q : s->next_seq)
+        if (q >= 0) return fail(DEDISP_ERR_BUSY, "clustering must be set before the first submit");
+    if (!s->cluster_on) {
+        const size_t ws = dd::cluster_workspace_bytes(s->capacity, static_cast<int32_t>(s->ndm_max),
+                                                      s->W.n);
+        hipError_t e = hipSuccess;
+        for (Slot& sl : s->slots) {
+            if (e == hipSuccess) e = hipMalloc(&sl.cl_ws, ws);
+            if (e == hipSuccess)
+                e = hipMalloc(&sl.d_clusters, static_cast<size_t>(s->capacity) * sizeof(dedisp_cluster));
+        }
+        if (e != hipSuccess) {
+            for (Slot& sl : s->slots) {
+                if (sl.cl_ws) (void)hipFree(sl.cl_ws);
+                if (sl.d_clusters) (void)hipFree(sl.d_clusters);
+                sl.cl_ws = nullptr;
+                sl.d_clusters = nullptr;
+            }
+            return fail(e == hipErrorOutOfMemory ? DEDISP_ERR_OUT_OF_MEMORY : DEDISP_ERR_HIP,
+                        "clustering buffers: %s", hipGetErrorString(e));
+        }
+    }
+    s->cl_dm_radius = dm_radius;
+    s->cl_width_radius = width_radius;
+    s->cl_time_tol = time_tol;
+    s->cluster_on = true;
+    dd::clear_error();
     return DEDISP_OK;
 }
 

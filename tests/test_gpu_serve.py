@@ -200,3 +200,39 @@ def test_serve_scores_with_trained_model():
         log("chunk", k, "events", n, "scores", r["scores"][:4])
         assert r["scores"] is not None and len(r["scores"]) == n
         assert (sc.cpu().numpy() == r["scores"]).all()
+
+
+def test_serve_clusters_each_chunk():
+    """With clustering on, every result carries the clusters of its own
+    events, equal to the oracle's clustering of those events; set after the
+    first submit it is refused."""
+    from paper_1112_0065_amd import _lib as L
+    torch_dev()
+    nch = 3
+    fbs = [_stream(760 + b, nch, 90.0 + 20 * b) for b in range(2)]
+    plans = [L.dedisp_plan_create(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list) for fb in fbs]
+    budget = 40 * L.dedisp_serve_slot_bytes(plans, C, WIDTHS)
+    srv = L.dedisp_serve_create(plans, C, WIDTHS, K, budget)
+    L.dedisp_serve_set_clustering(srv, 2, 1, 0)
+    for k in range(nch):
+        for b, fb in enumerate(fbs):
+            while not L.dedisp_serve_submit(srv, b, k, _chunk(fb, k), L.dedisp_now_ns()):
+                time.sleep(0.01)
+    with pytest.raises(L.DedispError) as ei:
+        L.dedisp_serve_set_clustering(srv, 1, 1, 0)
+    assert ei.value.status == L.ERR_BUSY
+    res = _drain(srv, 2 * nch)
+    total_ev = total_cl = 0
+    for r in res:
+        assert r["flags"] & L.CHUNK_CLUSTERED and r["clusters"] is not None
+        _, ref = oracle.cluster_events(r["events"], WIDTHS, 2, 1, 0)
+        got = r["clusters"]
+        assert len(got) == len(ref)
+        for g, c in zip(got, ref):
+            assert tuple(int(g[k]) for k in oracle.CLUSTER_FIELDS[:-1]) == \
+                tuple(c[k] for k in oracle.CLUSTER_FIELDS[:-1]) and float(g["snr"]) == c["snr"]
+        total_ev += len(r["events"])
+        total_cl += len(got)
+    log(f"served {total_ev} events in {total_cl} clusters")
+    assert total_ev > total_cl > 0
+    srv.close()
