@@ -27,9 +27,11 @@ from .pipeline import search
 from .coincidence import zero_dm_series, rfi_mask, binomial_tail
 from .baseline import baseline_remove
 from .cluster import cluster_events, CLUSTER_FIELDS
+from .subband import subband_dedisperse, subband_plan, effective_delays
 
 __all__ = [
     "baseline_remove", "cluster_events", "CLUSTER_FIELDS",
+    "subband_dedisperse", "subband_plan", "effective_delays",
     "zero_dm_series", "rfi_mask", "binomial_tail",
     "K_DM", "channel_freqs", "delay_table", "max_delay", "nearest_tie_distance",
     "unpack_2bit", "dedisperse", "brute_dedisperse", "prefix_sum", "boxcar",
