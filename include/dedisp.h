@@ -410,6 +410,45 @@ int64_t dedisp_percentile_ns(const int64_t* sorted, int64_t n, double q);
 int32_t dedisp_serve_admission(size_t budget, size_t resident, size_t slot_bytes);
 
 /* ------------------------------------------------------------------------
+ * Subband (two-stage) dedispersion: a cheaper approximation of the direct
+ * method of section 2.2.  The band is split into nsub subbands of
+ * S = nchans / nsub channels (subband s starts at channel c0 = s * S);
+ * the plan's fine trials are grouped `group` at a time in list order, and
+ * group q's coarse DM is the DM of its middle trial, q * group +
+ * (size_q - 1) / 2.
+ *   stage 1: sub[s][q][t] = sum_{c' < S} x[c0 + c'][t + dsub[s][q][c']],
+ *     dsub the delay table of subband s as its own filterbank (top frequency
+ *     f_top + c0 * df, same df and tsamp, the coarse DMs, the plan's law and
+ *     rounding);
+ *   stage 2: out[d][t] = sum_s sub[s][q(d)][t + delay[d][c0]].
+ * Exact integers throughout; equal to direct dedispersion with the effective
+ * delay delay[d][c0] + dsub[s][q(d)][c - c0].  nsub = 1 with group = 1
+ * reproduces dedisp_execute exactly.
+ *
+ * create: plan = the fine-trial plan (must outlive the subband object);
+ *   nchans / nsub a multiple of 4; group in [1, 16].  Builds one plan per
+ *   subband.  UNSUPPORTED when a group's subband delays spread over more than
+ *   31 744 samples.
+ * info: max_delay = nsamps - nout of the output; ncoarse = coarse trials;
+ *   span = largest spread of a group's subband delays (samples).
+ * workspace_bytes: device bytes for nsamps samples (0 when too few).
+ * execute: in = device packed 2-bit input (time-major, as dedisp_execute);
+ *   out = device [ndm][nsamps - max_delay] (int32 or uint16); workspace
+ *   256-byte aligned, clobbered.  Asynchronous on `stream`.
+ * Errors: INVALID_ARG, TOO_FEW_SAMPLES, UNSUPPORTED, OUT_OF_MEMORY, HIP.
+ * ------------------------------------------------------------------------ */
+typedef struct dedisp_subband_s* dedisp_subband;
+dedisp_status dedisp_subband_create(dedisp_plan plan, int32_t nsub, int32_t group,
+                                    dedisp_subband* out);
+dedisp_status dedisp_subband_info(dedisp_subband b, int64_t* max_delay, int32_t* ncoarse,
+                                  int32_t* span);
+size_t dedisp_subband_workspace_bytes(dedisp_subband b, int64_t nsamps);
+dedisp_status dedisp_subband_execute(dedisp_subband b, const uint8_t* in, int64_t nsamps,
+                                     void* out, dedisp_out_type out_type, void* workspace,
+                                     dedisp_stream stream);
+dedisp_status dedisp_subband_destroy(dedisp_subband b);
+
+/* ------------------------------------------------------------------------
  * Event clustering across DM trials and widths.  Section 2.3 gathers the
  * above-cut samples of one series into events; one dispersed pulse crosses
  * the cut in many neighbouring trials and widths and so gives many events.

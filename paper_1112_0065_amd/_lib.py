@@ -107,6 +107,11 @@ def lib() -> C.CDLL:
         "dedisp_autotune": (i32, [vp, i64, i32, C.c_char_p, P(_Tile), P(i32)]),
         "dedisp_rfi_mask_workspace_bytes": (sz, [i32, i64]),
         "dedisp_cluster_workspace_bytes": (sz, [i64, i32, i32]),
+        "dedisp_subband_create": (i32, [vp, i32, i32, P(vp)]),
+        "dedisp_subband_info": (i32, [vp, P(i64), P(i32), P(i32)]),
+        "dedisp_subband_workspace_bytes": (sz, [vp, i64]),
+        "dedisp_subband_execute": (i32, [vp, vp, i64, vp, i32, vp, vp]),
+        "dedisp_subband_destroy": (i32, [vp]),
         "dedisp_write_candidates": (i32, [C.c_char_p, vp, i64, P(f64), i32, P(i32), i32, f64, i64,
                                           i32]),
         "dedisp_trigger_windows": (i32, [vp, i64, P(i32), i32, i32, f32, i32, i64, i64, vp, i64,
@@ -354,6 +359,49 @@ def events_from_buffer(buf, n: int) -> np.ndarray:
     if hasattr(raw, "cpu"):
         raw = raw.cpu().numpy()
     return np.frombuffer(np.asarray(raw, dtype=np.uint8).tobytes(), dtype=EVENT_DTYPE, count=n)
+
+
+# ---------------------------------------------------------------------------
+# Subband (two-stage) dedispersion
+# ---------------------------------------------------------------------------
+
+class Subband:
+    def __init__(self, handle: int, plan, nsub: int, group: int):
+        self.handle = handle
+        self.plan = plan            # keeps the fine-trial plan alive
+        self.nsub = nsub
+        self.group = group
+        md, nc, sp = C.c_int64(), C.c_int32(), C.c_int32()
+        _check(lib().dedisp_subband_info(handle, C.byref(md), C.byref(nc), C.byref(sp)))
+        self.max_delay, self.ncoarse, self.span = int(md.value), int(nc.value), int(sp.value)
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.dedisp_subband_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dedisp_subband_create(plan, nsub: int, group: int) -> Subband:
+    h = C.c_void_p()
+    _check(lib().dedisp_subband_create(plan.handle, int(nsub), int(group), C.byref(h)))
+    return Subband(h.value, plan, nsub, group)
+
+
+def dedisp_subband_workspace_bytes(sb: Subband, nsamps: int) -> int:
+    return int(lib().dedisp_subband_workspace_bytes(sb.handle, int(nsamps)))
+
+
+def dedisp_subband_execute(sb: Subband, packed, nsamps: int, out, workspace, stream=None):
+    """packed: device uint8; out: device [ndm][nsamps - sb.max_delay] int16 (uint16 bits) or
+    int32."""
+    _check(lib().dedisp_subband_execute(sb.handle, _ptr(packed), int(nsamps), _ptr(out),
+                                        _out_type(out), _ptr(workspace), _stream(stream)))
 
 
 # ---------------------------------------------------------------------------
