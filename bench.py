@@ -235,6 +235,8 @@ def main():
                        "hbm_frac": bl_bytes / (bl_ms * 1e-3) / 8e12}
     del flat
     rec["cluster"] = bench_cluster(evb, n_events, ndm, fb.widths)
+    rec["subband"] = bench_subband(fb, plan, inp, evb, n_events,
+                                   rec["stages_ms"]["repack"] + rec["stages_ms"]["dedisperse"])
     del out, ws, pws, evb, inp
     torch.cuda.empty_cache()
     if not args.no_multibeam:
@@ -362,6 +364,68 @@ def bench_serve(args):
             "batches": st["batches"], "mean_batch": st["mean_batch"], "max_batch": st["max_batch"],
             "slots": st["slots"], "busy_retries": busy, "wall_s": wall,
             "data": "4 fast-noise chunk payloads cycled over beams and sequence numbers"}
+
+
+def bench_subband(fb, plan, inp, evb, n_events, direct_ms):
+    """Subband dedispersion of the survey beam in place of the direct sum:
+    time per beam (repack + both stages, HIP events on the stream; direct_ms
+    is repack + direct dedispersion of the same beam), and what
+    the approximation costs: for each injected pulse, the best S/N of the
+    events near its trial and arrival, against the direct path's."""
+    import numpy as np
+    import torch
+
+    from paper_1112_0065_amd import _lib as L
+
+    ndm = len(fb.dm_list)
+    ev_direct = L.events_from_buffer(evb, n_events)
+
+    def best_snr(ev):
+        out = []
+        dmi, tpk = ev["dm_idx"].astype(np.int64), ev["t_peak"].astype(np.int64)
+        for pu in fb.pulses:
+            d = int(np.argmin(np.abs(fb.dm_list - pu.dm)))
+            near = (np.abs(dmi - d) <= 2) & (np.abs(tpk - pu.t0) <= pu.width + 2)
+            out.append(float(ev["snr"][near].max()) if near.any() else 0.0)
+        return np.array(out)
+
+    ref = best_snr(ev_direct)
+    res = {}
+    for nsub, group in ((32, 8), (16, 8), (64, 4)):
+        sb = L.dedisp_subband_create(plan, nsub, group)
+        nout = fb.nsamps - sb.max_delay
+        ws = torch.empty(L.dedisp_subband_workspace_bytes(sb, fb.nsamps), dtype=torch.uint8,
+                         device="cuda")
+        out = torch.empty((ndm, nout), dtype=torch.int16, device="cuda")
+        stream = torch.cuda.current_stream()
+        L.dedisp_subband_execute(sb, inp, fb.nsamps, out, ws, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record(stream)
+        for _ in range(reps):
+            L.dedisp_subband_execute(sb, inp, fb.nsamps, out, ws, stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        pws = torch.empty(L.find_peaks_workspace_bytes(ndm, nout, fb.widths), dtype=torch.uint8,
+                          device="cuda")
+        eb = torch.empty((1 << 20) * 40, dtype=torch.uint8, device="cuda")
+        n = L.find_peaks(out, ndm, nout, fb.widths, fb.snr_thresh, eb, 1 << 20, pws)
+        got = best_snr(L.events_from_buffer(eb, n))
+        found = ref > 0
+        ratio = got[found] / ref[found]
+        res[f"{nsub}x{group}"] = {
+            "nsub": nsub, "group": group, "ncoarse": sb.ncoarse, "stage1_tile": list(sb.tile),
+            "ms": ms,
+            "dm_trial_samples_per_s": ndm * nout / (ms * 1e-3),
+            "speedup_vs_direct": direct_ms / ms, "events": n,
+            "pulses_found_direct": int(found.sum()), "pulses_found": int((got[found] > 0).sum()),
+            "snr_ratio_median": float(np.median(ratio)), "snr_ratio_min": float(ratio.min())}
+        del ws, out, pws, eb
+        sb.close()
+        torch.cuda.empty_cache()
+    return res
 
 
 def bench_cluster(evb, n_events, ndm, widths):

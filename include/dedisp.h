@@ -428,9 +428,13 @@ int32_t dedisp_serve_admission(size_t budget, size_t resident, size_t slot_bytes
  * create: plan = the fine-trial plan (must outlive the subband object);
  *   nchans / nsub a multiple of 4; group in [1, 16].  Builds one plan per
  *   subband.  UNSUPPORTED when a group's subband delays spread over more than
- *   31 744 samples.
+ *   31 728 samples.
+ *   Stage 1 sums few channels per output, so create tunes its tile shape
+ *   (dedisp_autotune, bit-exact candidates only) on the subband with the
+ *   largest delays and uses it for every subband whose LDS tile it fits.
  * info: max_delay = nsamps - nout of the output; ncoarse = coarse trials;
- *   span = largest spread of a group's subband delays (samples).
+ *   span = largest spread of a group's subband delays (samples); tile = the
+ *   stage-1 tile shape of that subband.  Any output may be NULL.
  * workspace_bytes: device bytes for nsamps samples (0 when too few).
  * execute: in = device packed 2-bit input (time-major, as dedisp_execute);
  *   out = device [ndm][nsamps - max_delay] (int32 or uint16); workspace
@@ -441,7 +445,7 @@ typedef struct dedisp_subband_s* dedisp_subband;
 dedisp_status dedisp_subband_create(dedisp_plan plan, int32_t nsub, int32_t group,
                                     dedisp_subband* out);
 dedisp_status dedisp_subband_info(dedisp_subband b, int64_t* max_delay, int32_t* ncoarse,
-                                  int32_t* span);
+                                  int32_t* span, dedisp_tile* tile);
 size_t dedisp_subband_workspace_bytes(dedisp_subband b, int64_t nsamps);
 dedisp_status dedisp_subband_execute(dedisp_subband b, const uint8_t* in, int64_t nsamps,
                                      void* out, dedisp_out_type out_type, void* workspace,

@@ -108,7 +108,7 @@ def lib() -> C.CDLL:
         "dedisp_rfi_mask_workspace_bytes": (sz, [i32, i64]),
         "dedisp_cluster_workspace_bytes": (sz, [i64, i32, i32]),
         "dedisp_subband_create": (i32, [vp, i32, i32, P(vp)]),
-        "dedisp_subband_info": (i32, [vp, P(i64), P(i32), P(i32)]),
+        "dedisp_subband_info": (i32, [vp, P(i64), P(i32), P(i32), P(_Tile)]),
         "dedisp_subband_workspace_bytes": (sz, [vp, i64]),
         "dedisp_subband_execute": (i32, [vp, vp, i64, vp, i32, vp, vp]),
         "dedisp_subband_destroy": (i32, [vp]),
@@ -371,9 +371,10 @@ class Subband:
         self.plan = plan            # keeps the fine-trial plan alive
         self.nsub = nsub
         self.group = group
-        md, nc, sp = C.c_int64(), C.c_int32(), C.c_int32()
-        _check(lib().dedisp_subband_info(handle, C.byref(md), C.byref(nc), C.byref(sp)))
+        md, nc, sp, t = C.c_int64(), C.c_int32(), C.c_int32(), _Tile()
+        _check(lib().dedisp_subband_info(handle, C.byref(md), C.byref(nc), C.byref(sp), C.byref(t)))
         self.max_delay, self.ncoarse, self.span = int(md.value), int(nc.value), int(sp.value)
+        self.tile = (t.dms_per_block, t.groups, t.stage_chans)
 
     def close(self):
         if getattr(self, "handle", None) and _lib is not None:

@@ -42,16 +42,23 @@ constexpr int kS2LdsBytes = 64 * 1024;
 // Block (tile, group q): out[d][t] for the group's trials and t in the tile.
 // sub: uint16 series of subband s at sub + ncoarse * (s * nsamps - cum[s]),
 // rows of nsamps - maxd[s] samples (the stage-1 output of each subband).
-// lo[q][s]: smallest delay[d][c0(s)] over the group; LDS row k holds samples
-// [t0 + lo, t0 + lo + row_len) of subband sc0 + k.
+// lo[q][s]: smallest delay[d][c0(s)] over the group.  The samples
+// [t0 + lo, t0 + lo + row_len) of subband sc0 + k are staged in LDS row k with
+// 16-byte loads from the 16-byte boundary at or before the first one; that
+// sample sits at LDS index mis (0..7) of the row, and mis is folded into the
+// trials' read offsets, which are block-uniform and come from scalar loads of
+// the delay tables, so that all reads of a subband issue back to back.  Chunks that reach past the row end load sample by
+// sample (positions past it read as 0; they only feed outputs past nout).
+constexpr int kS2MaxChunk = 16;
+
 template <int GM, bool OUT16>
 __global__ __launch_bounds__(kS2Threads) void subband_sum_kernel(
     const uint16_t* __restrict__ sub, const int64_t* __restrict__ cum,
     const int32_t* __restrict__ maxd, const int32_t* __restrict__ inter,
     const int32_t* __restrict__ lo, int nsub, int ncoarse, int ndm, int group, int64_t nsamps,
-    int64_t nout, int row_len, int chunk, void* __restrict__ out) {
-    extern __shared__ uint16_t rows[];
-    __shared__ int32_t s_off[kMaxGroup * 8];
+    int64_t nout, int row_len, int row_stride, int chunk, void* __restrict__ out) {
+    extern __shared__ uint4 rows_raw[];
+    uint16_t* rows = reinterpret_cast<uint16_t*>(rows_raw);
     const int q = blockIdx.y;
     const int64_t t0 = static_cast<int64_t>(blockIdx.x) * kS2Tile;
     const int d0 = q * group;
@@ -65,35 +72,54 @@ __global__ __launch_bounds__(kS2Threads) void subband_sum_kernel(
 
     for (int sc0 = 0; sc0 < nsub; sc0 += chunk) {
         const int nsc = min(chunk, nsub - sc0);
-        if (tid < kMaxGroup * 8) {
-            const int g = tid / 8, k = tid % 8;
-            if (g < gq && k < nsc)
-                s_off[tid] = inter[static_cast<int64_t>(d0 + g) * nsub + sc0 + k] -
-                             lo[static_cast<int64_t>(q) * nsub + sc0 + k];
-        }
         for (int k = 0; k < nsc; ++k) {
             const int s = sc0 + k;
             const int64_t nrow = nsamps - maxd[s];
             const uint16_t* row = sub + static_cast<int64_t>(ncoarse) * (s * nsamps - cum[s]) +
                                   static_cast<int64_t>(q) * nrow;
             const int64_t base = t0 + lo[static_cast<int64_t>(q) * nsub + s];
-            uint16_t* dst = rows + k * row_len;
-            for (int i = tid; i < row_len; i += kS2Threads) {
-                const int64_t idx = base + i;
-                dst[i] = idx < nrow ? row[idx] : static_cast<uint16_t>(0);
+            const uint16_t* first = row + base;
+            const int mis = static_cast<int>((reinterpret_cast<uintptr_t>(first) >> 1) & 7);
+            const uint16_t* a0 = first - mis;                 // 16-byte aligned
+            const int nchunk = (mis + row_len + 7) >> 3;
+            const int64_t valid = nrow - base + mis;           // a0[i] is in the row for i < valid
+            uint16_t* dst = rows + k * row_stride;
+            for (int c = tid; c < nchunk; c += kS2Threads) {
+                const int64_t i0 = static_cast<int64_t>(c) * 8;
+                if (i0 + 8 <= valid) {
+                    reinterpret_cast<uint4*>(dst)[c] = *reinterpret_cast<const uint4*>(a0 + i0);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        dst[i0 + e] = (i0 + e >= mis && i0 + e < valid) ? a0[i0 + e] : static_cast<uint16_t>(0);
+                }
             }
         }
         __syncthreads();
         for (int k = 0; k < nsc; ++k) {
-            const uint16_t* src = rows + k * row_len + tid;
+            // read offsets (uniform: scalar loads); trials past the group's
+            // end repeat its last one and are never written
+            const int s = sc0 + k;
+            const int64_t nrow = nsamps - maxd[s];
+            const int64_t lo_qs = lo[static_cast<int64_t>(q) * nsub + s];
+            const uint16_t* first = sub + static_cast<int64_t>(ncoarse) * (s * nsamps - cum[s]) +
+                                    static_cast<int64_t>(q) * nrow + t0 + lo_qs;
+            const int mis = static_cast<int>((reinterpret_cast<uintptr_t>(first) >> 1) & 7);
+            const uint16_t* src = rows + k * row_stride + tid;
+            int off[GM];
 #pragma unroll
-            for (int g = 0; g < GM; ++g) {
-                if (g < gq) {
-                    const int off = s_off[g * 8 + k];
+            for (int g = 0; g < GM; ++g)
+                off[g] = inter[static_cast<int64_t>(d0 + min(g, gq - 1)) * nsub + s] -
+                         static_cast<int>(lo_qs) + mis;
+            uint32_t v[GM][kS2PerThread];
 #pragma unroll
-                    for (int j = 0; j < kS2PerThread; ++j) acc[g][j] += src[off + j * kS2Threads];
-                }
-            }
+            for (int g = 0; g < GM; ++g)
+#pragma unroll
+                for (int j = 0; j < kS2PerThread; ++j) v[g][j] = src[off[g] + j * kS2Threads];
+#pragma unroll
+            for (int g = 0; g < GM; ++g)
+#pragma unroll
+                for (int j = 0; j < kS2PerThread; ++j) acc[g][j] += v[g][j];
         }
         __syncthreads();
     }
@@ -187,6 +213,23 @@ extern "C" dedisp_status dedisp_subband_create(dedisp_plan plan, int32_t nsub, i
             free_subband(b);
             return st;
         }
+    }
+    // Stage 1 sums few channels per output, so its best tile shape differs
+    // from the direct sum's: tune it (bit-exact candidates only) on the
+    // subband with the largest delays and use it wherever its LDS tile fits.
+    int ref = 0;
+    for (int s = 1; s < nsub; ++s)
+        if (b->sub[s]->max_delay > b->sub[ref]->max_delay) ref = s;
+    dedisp_tile best{};
+    int32_t rejected = 0;
+    const int64_t tune_n = std::max<int64_t>(int64_t(1) << 17, b->sub[ref]->max_delay + (int64_t(1) << 15));
+    if (dedisp_autotune(b->sub[ref], tune_n, DEDISP_OUT_U16, nullptr, &best, &rejected) == DEDISP_OK) {
+        const dd::TileConfig c{best.dms_per_block, best.groups, best.stage_chans};
+        for (int s = 0; s < nsub; ++s)
+            if (s != ref && dd::tile_lds_bytes(b->sub[s], c) <= 160 * 1024)
+                b->sub[s]->tuned.store((c.dms_per_block << 16) | (c.groups << 8) | c.stage_chans);
+    }
+    for (int s = 0; s < nsub; ++s) {
         dedisp_status tst = DEDISP_OK;
         if (!dd::offset_table(b->sub[s], dd::default_tile_config(b->sub[s]), true, &tst)) {
             free_subband(b);
@@ -218,7 +261,7 @@ extern "C" dedisp_status dedisp_subband_create(dedisp_plan plan, int32_t nsub, i
             lo[static_cast<size_t>(q) * nsub + s] = mn;
             b->span = std::max(b->span, mx - mn);
         }
-    if (static_cast<int64_t>(kS2Tile + b->span) * 2 > kS2LdsBytes) {
+    if (static_cast<int64_t>(kS2Tile + b->span + 16) * 2 > kS2LdsBytes) {
         free_subband(b);
         return fail(DEDISP_ERR_UNSUPPORTED,
                     "a group's subband delays spread over %d samples: use smaller groups", b->span);
@@ -244,11 +287,18 @@ extern "C" dedisp_status dedisp_subband_create(dedisp_plan plan, int32_t nsub, i
 }
 
 extern "C" dedisp_status dedisp_subband_info(dedisp_subband b, int64_t* max_delay,
-                                             int32_t* ncoarse, int32_t* span) {
+                                             int32_t* ncoarse, int32_t* span, dedisp_tile* tile) {
     if (!b) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
     if (max_delay) *max_delay = b->loss;
     if (ncoarse) *ncoarse = b->ncoarse;
     if (span) *span = b->span;
+    if (tile) {
+        int ref = 0;
+        for (int s = 1; s < b->nsub; ++s)
+            if (b->sub[s]->max_delay > b->sub[ref]->max_delay) ref = s;
+        const dd::TileConfig c = dd::default_tile_config(b->sub[ref]);
+        *tile = dedisp_tile{c.dms_per_block, c.groups, c.stage_chans};
+    }
     return DEDISP_OK;
 }
 
@@ -288,9 +338,10 @@ extern "C" dedisp_status dedisp_subband_execute(dedisp_subband b, const uint8_t*
     }
     const int64_t nout = nsamps - b->loss;
     const int row_len = kS2Tile + b->span;
-    const int chunk = std::max(1, std::min(8, kS2LdsBytes / (row_len * 2)));
+    const int row_stride = (row_len + 7 + 7) & ~7;        // room for the leading misalignment
+    const int chunk = std::max(1, std::min(kS2MaxChunk, kS2LdsBytes / (row_stride * 2)));
     const dim3 grid(static_cast<unsigned>((nout + kS2Tile - 1) / kS2Tile), static_cast<unsigned>(b->ncoarse));
-    const size_t lds = static_cast<size_t>(chunk) * row_len * 2;
+    const size_t lds = static_cast<size_t>(chunk) * row_stride * 2;
     const bool u16 = out_type == DEDISP_OUT_U16;
 #define DD_S2(GM_)                                                                             \
     if (b->group <= GM_) {                                                                     \
@@ -298,12 +349,12 @@ extern "C" dedisp_status dedisp_subband_execute(dedisp_subband b, const uint8_t*
             hipLaunchKernelGGL((subband_sum_kernel<GM_, true>), grid, dim3(kS2Threads), lds,   \
                                stream, series, b->d_cum, b->d_maxd, b->d_inter, b->d_lo,      \
                                b->nsub, b->ncoarse, p->ndm, b->group, nsamps, nout, row_len,   \
-                               chunk, out);                                                    \
+                               row_stride, chunk, out);                                                    \
         else                                                                                   \
             hipLaunchKernelGGL((subband_sum_kernel<GM_, false>), grid, dim3(kS2Threads), lds,  \
                                stream, series, b->d_cum, b->d_maxd, b->d_inter, b->d_lo,      \
                                b->nsub, b->ncoarse, p->ndm, b->group, nsamps, nout, row_len,   \
-                               chunk, out);                                                    \
+                               row_stride, chunk, out);                                                    \
     } else
     DD_S2(1) DD_S2(2) DD_S2(4) DD_S2(8) DD_S2(16) {}
 #undef DD_S2
