@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--out-i32", action="store_true", help="int32 series instead of uint16")
     ap.add_argument("--no-multibeam", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the baseline-removal, clustering, subband and coincidence-mask legs")
     ap.add_argument("--serve-chunks", type=int, default=3, help="chunks per beam when streaming")
     ap.add_argument("--serve-unpaced-chunks", type=int, default=16,
                     help="chunks per beam in the unpaced streaming run")
@@ -216,35 +218,37 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
-    # baseline removal (running mean, radius 2048) of the survey series: one
-    # read and one write of the uint16 rows
-    R = 2048
-    flat = torch.empty((ndm, nout - 2 * R), dtype=torch.int16, device="cuda")
-    L.baseline_remove(out, ndm, nout, R, 3 * fb.nchans, flat)
-    torch.cuda.synchronize()
-    b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    b0.record()
-    for _ in range(10):
+    if not args.no_next:
+        # baseline removal (running mean, radius 2048) of the survey series: one
+        # read and one write of the uint16 rows
+        R = 2048
+        flat = torch.empty((ndm, nout - 2 * R), dtype=torch.int16, device="cuda")
         L.baseline_remove(out, ndm, nout, R, 3 * fb.nchans, flat)
-    b1.record()
-    b1.synchronize()
-    bl_ms = b0.elapsed_time(b1) / 10
-    bl_bytes = ndm * nout * 2 + ndm * (nout - 2 * R) * 2
-    rec["baseline"] = {"radius": R, "ms": bl_ms, "algorithmic_bytes": bl_bytes,
-                       "achieved_GBps": bl_bytes / (bl_ms * 1e-3) / 1e9,
-                       "hbm_frac": bl_bytes / (bl_ms * 1e-3) / 8e12}
-    del flat
-    rec["cluster"] = bench_cluster(evb, n_events, ndm, fb.widths)
-    rec["subband"] = bench_subband(fb, plan, inp, evb, n_events,
-                                   rec["stages_ms"]["repack"] + rec["stages_ms"]["dedisperse"])
+        torch.cuda.synchronize()
+        b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        b0.record()
+        for _ in range(10):
+            L.baseline_remove(out, ndm, nout, R, 3 * fb.nchans, flat)
+        b1.record()
+        b1.synchronize()
+        bl_ms = b0.elapsed_time(b1) / 10
+        bl_bytes = ndm * nout * 2 + ndm * (nout - 2 * R) * 2
+        rec["baseline"] = {"radius": R, "ms": bl_ms, "algorithmic_bytes": bl_bytes,
+                           "achieved_GBps": bl_bytes / (bl_ms * 1e-3) / 1e9,
+                           "hbm_frac": bl_bytes / (bl_ms * 1e-3) / 8e12}
+        del flat
+        rec["cluster"] = bench_cluster(evb, n_events, ndm, fb.widths)
+        rec["subband"] = bench_subband(fb, plan, inp, evb, n_events,
+                                       rec["stages_ms"]["repack"] + rec["stages_ms"]["dedisperse"])
     del out, ws, pws, evb, inp
     torch.cuda.empty_cache()
     if not args.no_multibeam:
         print("13-beam batch ...", file=sys.stderr, flush=True)
         rec["multibeam"] = bench_multibeam(args)
         rec["rtf_13beam"] = rec["multibeam"]["rtf_batch"]
-    print("13-beam coincidence mask ...", file=sys.stderr, flush=True)
-    rec["rfi_mask"] = bench_rfi_mask(args)
+    if not args.no_next:
+        print("13-beam coincidence mask ...", file=sys.stderr, flush=True)
+        rec["rfi_mask"] = bench_rfi_mask(args)
     if not args.no_serve:
         print("13-beam streaming at the real-time rate ...", file=sys.stderr, flush=True)
         rec["serve"] = bench_serve(args)
