@@ -24,7 +24,7 @@ from .sigma_cut import (series_stats, threshold_level, snr_value, exact_k,
                         is_event)
 from .peaks import find_runs, find_events, EVENT_FIELDS
 from .pipeline import search
-from .coincidence import zero_dm_series, rfi_mask, binomial_tail
+from .coincidence import zero_dm_series, rfi_mask, binomial_tail, replace_masked
 from .baseline import baseline_remove
 from .cluster import cluster_events, CLUSTER_FIELDS
 from .subband import subband_dedisperse, subband_plan, effective_delays
@@ -32,7 +32,7 @@ from .subband import subband_dedisperse, subband_plan, effective_delays
 __all__ = [
     "baseline_remove", "cluster_events", "CLUSTER_FIELDS",
     "subband_dedisperse", "subband_plan", "effective_delays",
-    "zero_dm_series", "rfi_mask", "binomial_tail",
+    "zero_dm_series", "rfi_mask", "binomial_tail", "replace_masked",
     "K_DM", "channel_freqs", "delay_table", "max_delay", "nearest_tie_distance",
     "unpack_2bit", "dedisperse", "brute_dedisperse", "prefix_sum", "boxcar",
     "n_boxcar", "series_stats", "threshold_level", "snr_value", "exact_k",

@@ -52,3 +52,16 @@ def binomial_tail(nbeams: int, p: float, m: int) -> float:
     """P(at least m of nbeams independent beams exceed), each with chance p."""
     return sum(math.comb(nbeams, j) * p ** j * (1.0 - p) ** (nbeams - j)
                for j in range(m, nbeams + 1))
+
+
+def replace_masked(x: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    """Apply the mask to one beam's levels x[c][t] (reading: a flagged sample
+    is replaced by the mean level in every channel).  The 2-bit quantiser is
+    symmetric, so its mean level is 1.5; even channels get level 1 and odd
+    channels level 2, which keeps every sample's channel sum at exactly
+    1.5 * nchans.  Returns a new array."""
+    y = np.array(x, dtype=np.uint8, copy=True)
+    m = np.asarray(mask, dtype=bool)
+    fill = np.where(np.arange(y.shape[0]) % 2 == 0, 1, 2).astype(np.uint8)
+    y[:, m] = fill[:, None]
+    return y

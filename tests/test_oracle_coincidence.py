@@ -94,3 +94,57 @@ def test_common_impulses_are_masked_and_nothing_else():
     assert mask.any() and not (mask & ~inside).any()
     # single-beam signals (the dispersed pulses) never reach 4 beams
     assert (votes[~inside] < 4).all()
+
+
+def test_replacement_keeps_the_mean_level_exactly():
+    rng = np.random.default_rng(21)
+    x = rng.integers(0, 4, size=(12, 50), dtype=np.uint8)
+    mask = np.zeros(50, bool)
+    mask[[0, 7, 8, 49]] = True
+    y = oracle.replace_masked(x, mask)
+    assert (y[:, ~mask] == x[:, ~mask]).all()
+    assert (y[:, mask] == np.array([1, 2] * 6, np.uint8)[:, None]).all()
+    assert (y[:, mask].sum(axis=0) == 18).all()          # 1.5 * 12 channels
+    # 1.5 is the quantiser's mean level: its edges are symmetric about 0
+    q = synth.quantise(np.random.default_rng(3).standard_normal(400000))
+    assert abs(q.mean() - 1.5) < 0.005
+    lo, mid, hi = synth.QUANT_EDGES
+    assert lo == -hi and mid == 0.0
+
+
+def test_applied_mask_removes_common_impulses_and_keeps_pulses():
+    """64 channels, 13 beams with common zero-DM impulses: after the mask is
+    applied no sample is flagged again, the low-DM events of the impulses
+    are gone, and the dispersed pulse of beam 0 keeps >= 90% of its S/N at
+    its trial (masked impulse samples inside its sweep cost a little)."""
+    nsamps, nchans = 1 << 14, 64
+    beams, imps, amps, pulses = synth.make_coincidence_beams(5, nsamps=nsamps, nchans=nchans,
+                                                             npulses=1, impulse_rate=30.0,
+                                                             dm_max=60.0)
+    assert len(imps) >= 10
+    z = [oracle.zero_dm_series(b, nsamps, nchans) for b in beams]
+    mask, votes, thr = oracle.rfi_mask(z, 3.0, 4)
+    assert mask.sum() > 0
+    x0 = oracle.unpack_2bit(beams[0], nsamps, nchans)
+    y0 = oracle.replace_masked(x0, mask)
+    ys = [oracle.replace_masked(oracle.unpack_2bit(b, nsamps, nchans), mask) for b in beams]
+    z2 = [y.sum(axis=0, dtype=np.int64) for y in ys]
+    mask2, _, _ = oracle.rfi_mask(z2, 3.0, 4)
+    assert not (mask2 & mask).any()
+    dms = np.linspace(0.0, 60.0, 31)
+    dly = oracle.delay_table(nchans, synth.F_TOP, -400.0 / nchans, synth.TSAMP, dms)
+    widths = [1, 2, 4, 8]
+    ev_before = oracle.find_events(oracle.boxcar(oracle.dedisperse(x0, dly), widths), 6.0)
+    ev_after = oracle.find_events(oracle.boxcar(oracle.dedisperse(y0, dly), widths), 6.0)
+    near_imp = lambda ev: sum(1 for e in ev if e[1] <= 1 and
+                              any(abs(e[4] - im.t) <= 8 for im in imps))
+    assert near_imp(ev_before) > 0 and near_imp(ev_after) == 0
+    p = pulses[0][0]
+    d = int(np.argmin(np.abs(dms - p.dm)))
+    wi = max(i for i, w in enumerate(widths) if w <= p.width)
+
+    def snr(x):
+        b = oracle.boxcar(oracle.dedisperse(x, dly[d:d + 1]), widths)[wi, 0]
+        return (b[p.t0 - 16:p.t0 + p.width + 16].max() - b.mean()) / b.std()
+    before, after = snr(x0), snr(y0)
+    assert before > 5.0 and after >= 0.9 * before, (before, after)
