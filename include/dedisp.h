@@ -555,6 +555,16 @@ dedisp_status dedisp_rfi_mask(const uint8_t* const* in_2bit, int32_t nbeams, int
                               int64_t* n_masked, void* workspace, dedisp_stream stream);
 dedisp_status dedisp_rfi_mask_read_stats(const void* workspace, int32_t nbeams, int64_t nsamps,
                                          int32_t* zero_dm, int64_t* thr, dedisp_stream stream);
+/* Apply the mask (reading of section 2.1, which leaves the use of the mask
+ * open): every flagged sample of every beam is replaced, in place, by the
+ * mean level of the symmetric 2-bit quantiser in every channel -- level 1 in
+ * even and level 2 in odd channels, so each channel pair sums to 3 and the
+ * sample's zero-DM sum is exactly 1.5 * nchans.  beams_2bit: host array of
+ * nbeams device pointers to packed time-major 2-bit data (modified); mask:
+ * device, nsamps bytes (nonzero = flagged), as dedisp_rfi_mask writes it.
+ * Asynchronous on `stream`.  Errors: INVALID_ARG, HIP. */
+dedisp_status dedisp_rfi_apply(uint8_t* const* beams_2bit, int32_t nbeams, int32_t nchans,
+                               int64_t nsamps, const uint8_t* mask, dedisp_stream stream);
 
 /* ------------------------------------------------------------------------
  * Learned triage (section 2.1: interference can swamp detection with false

@@ -121,6 +121,7 @@ def lib() -> C.CDLL:
         "baseline_remove": (i32, [vp, i32, i32, i64, i32, i32, vp, i32, vp]),
         "dedisp_rfi_mask": (i32, [P(vp), i32, i32, i64, f32, i32, vp, P(i64), vp, vp]),
         "dedisp_rfi_mask_read_stats": (i32, [vp, i32, i64, P(i32), P(i64), vp]),
+        "dedisp_rfi_apply": (i32, [P(vp), i32, i32, i64, vp, vp]),
         "dedisp_serve_slot_bytes": (sz, [P(vp), i32, i64, P(i32), i32]),
         "dedisp_serve_create": (i32, [P(vp), i32, i64, P(i32), i32, f32, sz, vp, P(vp)]),
         "dedisp_serve_submit": (i32, [vp, i32, i64, vp, i64]),
@@ -488,6 +489,14 @@ def dedisp_rfi_mask(inputs, nchans: int, nsamps: int, k_sigma: float, min_beams:
                                  int(min_beams), _ptr(mask), C.byref(n), _ptr(workspace),
                                  _stream(stream)))
     return int(n.value)
+
+
+def dedisp_rfi_apply(beams, nchans: int, nsamps: int, mask, stream=None):
+    """Replace the flagged samples of every beam (device uint8 tensors, in
+    place) by the mean level in every channel."""
+    arr = (C.c_void_p * len(beams))(*[_ptr(t) for t in beams])
+    _check(lib().dedisp_rfi_apply(arr, len(beams), int(nchans), int(nsamps), _ptr(mask),
+                                  _stream(stream)))
 
 
 def dedisp_rfi_mask_read_stats(workspace, nbeams: int, nsamps: int, stream=None):

@@ -185,6 +185,35 @@ bool coinc_args_ok(int32_t nbeams, int32_t nchans, int64_t nsamps) {
 
 }  // namespace
 
+namespace {
+
+// Masked samples take the mean level 1.5 in every channel: levels 1 and 2 in
+// alternate channels (byte 0x99: channels 4k and 4k + 2 at level 1, 4k + 1
+// and 4k + 3 at level 2).  One thread per (beam, sample); flagged samples are
+// rare, so the write is a short loop over the sample's bytes.
+struct BeamPtrs {
+    uint8_t* p[64];
+};
+
+__global__ __launch_bounds__(kCThreads) void rfi_apply_kernel(BeamPtrs beams, int nbeams,
+                                                              int64_t nsamps, int bytes_per_sample,
+                                                              const uint8_t* __restrict__ mask) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kCThreads + threadIdx.x;
+    if (i >= nsamps * nbeams) return;
+    const int b = static_cast<int>(i / nsamps);
+    const int64_t t = i - static_cast<int64_t>(b) * nsamps;
+    if (!mask[t]) return;
+    uint8_t* row = beams.p[b] + t * bytes_per_sample;
+    if ((bytes_per_sample & 15) == 0 && (reinterpret_cast<uintptr_t>(row) & 15) == 0) {
+        const uint4 v = make_uint4(0x99999999u, 0x99999999u, 0x99999999u, 0x99999999u);
+        for (int k = 0; k < bytes_per_sample / 16; ++k) reinterpret_cast<uint4*>(row)[k] = v;
+    } else {
+        for (int k = 0; k < bytes_per_sample; ++k) row[k] = 0x99;
+    }
+}
+
+}  // namespace
+
 extern "C" size_t dedisp_rfi_mask_workspace_bytes(int32_t nbeams, int64_t nsamps) {
     if (nbeams < 1 || nbeams > 64 || nsamps < 1 || nsamps >= (int64_t(1) << 31)) return 0;
     return coinc_layout(nbeams, nsamps).bytes;
@@ -260,5 +289,26 @@ extern "C" dedisp_status dedisp_rfi_mask_read_stats(const void* workspace, int32
         DD_HIP(hipMemcpyAsync(thr, w + l.o_thr, static_cast<size_t>(nbeams) * 8,
                               hipMemcpyDeviceToHost, stream));
     DD_HIP(hipStreamSynchronize(stream));
+    return DEDISP_OK;
+}
+
+extern "C" dedisp_status dedisp_rfi_apply(uint8_t* const* beams_2bit, int32_t nbeams,
+                                          int32_t nchans, int64_t nsamps, const uint8_t* mask,
+                                          dedisp_stream stream) {
+    using dd::fail;
+    if (!beams_2bit || !mask) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
+    if (!coinc_args_ok(nbeams, nchans, nsamps))
+        return fail(DEDISP_ERR_INVALID_ARG,
+                    "need 1 <= nbeams <= 64, nchans a multiple of 4 in [4, 21844], 1 <= nsamps < 2^31");
+    BeamPtrs ptrs{};
+    for (int b = 0; b < nbeams; ++b) {
+        if (!beams_2bit[b]) return fail(DEDISP_ERR_INVALID_ARG, "beam %d is NULL", b);
+        ptrs.p[b] = beams_2bit[b];
+    }
+    const int64_t n = nsamps * nbeams;
+    hipLaunchKernelGGL(rfi_apply_kernel, dim3(static_cast<unsigned>((n + kCThreads - 1) / kCThreads)),
+                       dim3(kCThreads), 0, stream, ptrs, nbeams, nsamps, nchans / 4, mask);
+    DD_HIP(hipGetLastError());
+    dd::clear_error();
     return DEDISP_OK;
 }

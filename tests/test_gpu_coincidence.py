@@ -81,3 +81,38 @@ def test_bad_arguments():
             L.dedisp_rfi_mask([p], *args, mask, ws)
         assert e.value.status == st
     assert L.dedisp_rfi_mask_workspace_bytes(65, 100) == 0
+
+
+@pytest.mark.parametrize("nchans,aligned", [(1024, True), (64, True), (20, True), (1024, False)])
+def test_apply_matches_oracle(nchans, aligned):
+    """The mask computed on the GPU, applied on the GPU in place, equals the
+    oracle's replacement of the flagged samples, byte for byte, on 16-byte
+    rows, short rows and misaligned buffers."""
+    from paper_1112_0065_amd import _lib as L
+    torch = torch_dev()
+    nsamps = 1 << 14
+    packed, imps, amps, _ = synth.make_coincidence_beams(8, nbeams=13, nsamps=nsamps, nchans=nchans,
+                                                         impulse_rate=20.0)
+    zs = [oracle.zero_dm_series(p, nsamps, nchans) for p in packed]
+    ref_mask, _, _ = oracle.rfi_mask(zs, 3.0, 4)
+    assert ref_mask.sum() > 0
+    bufs = []
+    for p in packed:
+        if aligned:
+            bufs.append(to_dev(p))
+        else:                                  # a view one byte into a larger buffer
+            big = to_dev(np.concatenate([np.zeros(1, np.uint8), p]))
+            bufs.append(big[1:])
+    ws = torch.empty(L.dedisp_rfi_mask_workspace_bytes(13, nsamps), dtype=torch.uint8, device="cuda")
+    mask = torch.empty(nsamps, dtype=torch.uint8, device="cuda")
+    L.dedisp_rfi_mask(bufs, nchans, nsamps, 3.0, 4, mask, ws)
+    L.dedisp_rfi_apply(bufs, nchans, nsamps, mask)
+    torch.cuda.synchronize()
+    for b, p in enumerate(packed):
+        want = oracle.replace_masked(oracle.unpack_2bit(p, nsamps, nchans), ref_mask)
+        got = oracle.unpack_2bit(bufs[b].cpu().numpy(), nsamps, nchans)
+        assert (got == want).all(), b
+    # applied data no longer flags the same samples
+    n2 = L.dedisp_rfi_mask(bufs, nchans, nsamps, 3.0, 4, mask, ws)
+    assert not (mask.cpu().numpy().astype(bool) & ref_mask).any()
+    log(f"nchans {nchans}: {int(ref_mask.sum())} samples replaced, {n2} flagged after")
