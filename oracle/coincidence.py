@@ -12,7 +12,7 @@ Readings (the paper leaves them open):
   * the series of a beam is its zero-DM series z_b[t] = sum_c x_b[c][t] over
     the samples all beams cover;
   * mean and sigma are the population statistics of z_b over those samples;
-  * "exceeds k sigma" is the strict S/N > k of the sigma-cut, decided
+  * exceeding k sigma means the strict S/N > k of the sigma-cut, decided
     exactly with the same integer threshold (sigma_cut.threshold_level); a
     constant series never exceeds.
 """

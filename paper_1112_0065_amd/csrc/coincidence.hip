@@ -10,7 +10,7 @@
 // Readings taken here: the per-beam series is the zero-DM series z_b[t] =
 // sum_c x_b[c][t] of the beam's 2-bit samples over the common sample range;
 // mean and sigma are the population statistics of z_b over that range, from
-// exact integer sums; "exceeds k sigma" is the strict S/N > k decided exactly
+// exact integer sums; exceeding k sigma means the strict S/N > k, decided exactly
 // as in the sigma-cut (z >= ceil((S1 + isqrt(floor(k^2 D)) + 1) / n)).
 //
 // Kernels: zero-DM sums straight from the packed bytes (popcounts of the two

@@ -19,7 +19,7 @@ def test_unpack_golden_layout():
 
 
 def test_paper_data_rate():
-    # Section 1: 2 bits per sample is "around 4 MB/s per beam" for 1024 ch / 64 us.
+    # Section 1 puts the 2-bit data rate of one beam at about 4 MB/s (1024 ch, 64 us).
     assert bytes_per_second(1024, 64e-6) == pytest.approx(4.0e6, rel=1e-12)
 
 
