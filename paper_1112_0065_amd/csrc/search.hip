@@ -718,17 +718,23 @@ __device__ __forceinline__ void write_segment(const T* __restrict__ in, int ndm,
     __syncthreads();
     const uint32_t total = wb[W.n];
     if (total <= static_cast<uint32_t>(kMaxStarts)) {
-        for (int i = threadIdx.x; i < npos; i += kThreads) {
-            const uint32_t p1 = pl[i + 1], p0 = pl[i];
-            for (int wi = 0; wi < W.n; ++wi) {
-                if (wc[wi] == 0) continue;
-                const int w = W.w[wi];
-                const uint32_t thr = wthr[wi];
-                const bool above = pl[i + 1 + w] - p1 >= thr;
-                const bool prev = (s0 + i > 0) && (pl[i + w] - p0 >= thr);
-                if (above && !prev) {
-                    const uint32_t k = atomicAdd(&wfill[wi], 1u);
-                    if (k < wc[wi]) starts[wb[wi] + k] = i;
+        // width outer (uniform), four positions per step: as in the count pass
+        for (int wi = 0; wi < W.n; ++wi) {
+            if (wc[wi] == 0) continue;
+            const int w = W.w[wi];
+            const uint32_t thr = wthr[wi];
+            for (int i0 = threadIdx.x; i0 < npos; i0 += 4 * kThreads) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = i0 + q * kThreads;
+                    if (i < npos) {
+                        const bool above = pl[i + 1 + w] - pl[i + 1] >= thr;
+                        const bool prev = (s0 + i > 0) && (pl[i + w] - pl[i] >= thr);
+                        if (above && !prev) {
+                            const uint32_t k = atomicAdd(&wfill[wi], 1u);
+                            if (k < wc[wi]) starts[wb[wi] + k] = i;
+                        }
+                    }
                 }
             }
         }
