@@ -8,30 +8,58 @@
 //         level of sample 32j+b of channel c.  Samples >= nsamps and the two
 //         trailing words are zero.
 //
-// One block moves a tile of 64 samples x 256 channels: a coalesced load into
-// LDS, then each wave turns one 4-byte column (16 channels x 64 samples) into
-// bit-planes with wave ballots -- bit k of every lane's word at once.
-// The kernel is HBM-bound: it reads and writes nsamps*nchans/4 bytes each.
+// One block covers a tile of 512 samples x 256 channels (64 bytes per input
+// row, 16 output words per channel).  The input rows are staged in LDS with
+// 16-byte loads.  Each wave then takes 16-channel columns of 64-sample
+// sub-tiles: lane b holds the 32-bit word of sample b (16 channels x 2 bits),
+// and a 32 x 32 bit transpose within each half-wave (five swizzle-and-mask
+// stages) leaves in lane k the plane (k & 1) of channel k >> 1 for the half's
+// 32 samples -- one output word.  The words go to an LDS output tile, from
+// which every channel row is written as 128 contiguous bytes.  The kernel is
+// bound by HBM: it reads and writes nsamps*nchans/4 bytes each.
+#include <algorithm>
+
 #include "dedisp_internal.hpp"
 
 namespace {
 
-constexpr int kTileT = 64;      // samples per tile (one wave64 ballot)
-constexpr int kTileC = 256;     // channels per tile = 64 bytes per row
+constexpr int kTileT = 512;               // samples per tile
+constexpr int kTileC = 256;               // channels per tile = 64 bytes per row
+constexpr int kTileW = kTileT / 32;       // output words per channel per tile
+constexpr int kOutStride = 2 * kTileW + 2;  // uint32 per channel in the output tile
+
+// One stage of the 32 x 32 bit transpose across the lanes of a half-wave:
+// lanes l and l ^ J exchange the J-bit blocks that the mask M selects.
+template <int J, uint32_t M>
+__device__ __forceinline__ uint32_t transpose_stage(uint32_t x, int lane) {
+    const uint32_t y = static_cast<uint32_t>(
+        __builtin_amdgcn_ds_swizzle(static_cast<int>(x), 0x1F | (J << 10)));
+    if (lane & J) return x ^ (((y >> J) ^ x) & M);
+    return x ^ ((((x >> J) ^ y) & M) << J);
+}
+
+constexpr int kInStride = kTileC / 16 + 1;               // uint32 per staged input row
+constexpr int kBufWords = kTileT * kInStride;              // = kTileC * kOutStride
+static_assert(kBufWords == kTileC * kOutStride, "input and output tiles share one buffer");
+constexpr int kPerWave = (kTileT / 64) * (kTileC / 16) / 4;   // (sub-tile, column) pairs per wave
 
 __global__ __launch_bounds__(256) void repack_2bit_kernel(const uint8_t* __restrict__ in,
                                                           int64_t nsamps, int nchans,
                                                           uint2* __restrict__ words,
-                                                          int64_t nwords, int vec16) {
-    __shared__ uint32_t tile[kTileT][kTileC / 16 + 1];  // padded row: no bank conflicts
+                                                          int64_t nwords, int64_t ntiles, int vec16,
+                                                          int st16) {
+    // the input tile, then (after every wave holds its words) the output tile
+    __shared__ uint32_t buf[kBufWords];
     const int tid = threadIdx.x;
-    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * kTileT;
-    const int c0 = blockIdx.y * kTileC;
-    const int row_bytes = nchans >> 2;
+    const int c0 = blockIdx.x * kTileC;          // channel tiles vary fastest: the blocks
+    const int row_bytes = nchans >> 2;           // of one row run together
+    for (int64_t tile = blockIdx.y; tile < ntiles; tile += gridDim.y) {
+    const int64_t t0 = tile * kTileT;
 
-    {   // load 64 rows x 64 bytes: thread -> (row, 16-byte chunk)
-        const int row = tid >> 2;
-        const int q = tid & 3;
+    // 1. 512 rows x 64 bytes: thread -> (row, 16-byte chunk), 8 chunks each
+    for (int r = tid; r < kTileT * 4; r += 256) {
+        const int row = r >> 2;
+        const int q = r & 3;
         const int64_t t = t0 + row;
         const int byte0 = (c0 >> 2) + q * 16;
         uint32_t v[4] = {0u, 0u, 0u, 0u};
@@ -46,36 +74,58 @@ __global__ __launch_bounds__(256) void repack_2bit_kernel(const uint8_t* __restr
             }
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) tile[row][q * 4 + i] = v[i];
+        for (int i = 0; i < 4; ++i) buf[row * kInStride + q * 4 + i] = v[i];
     }
     __syncthreads();
 
+    // 2. each wave takes the (sub-tile, column) pairs g = wave + 4n; lane b
+    //    holds sample b of the sub-tile
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int64_t j = t0 >> 5;  // first of the two 32-sample words this tile fills
-#pragma unroll 1
-    for (int k = 0; k < 4; ++k) {
-        const int col = wave * 4 + k;
-        const int cbase = c0 + col * 16;
-        if (cbase >= nchans) break;
-        const uint32_t x = tile[lane][col];
-        uint64_t mylo = 0, myhi = 0;
+    const int h = lane >> 5;      // half-wave: samples 0-31 or 32-63 of the sub-tile
+    const int k = lane & 31;
+    uint32_t xs[kPerWave];
 #pragma unroll
-        for (int ch = 0; ch < 16; ++ch) {
-            const uint64_t lo = __ballot((x >> (2 * ch)) & 1u);
-            const uint64_t hi = __ballot((x >> (2 * ch + 1)) & 1u);
-            if (lane == ch) { mylo = lo; myhi = hi; }
+    for (int n = 0; n < kPerWave; ++n) {
+        const int g = wave + 4 * n;
+        xs[n] = buf[(64 * (g / (kTileC / 16)) + lane) * kInStride + g % (kTileC / 16)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int n = 0; n < kPerWave; ++n) {
+        const int g = wave + 4 * n;
+        const int sub = g / (kTileC / 16);
+        const int col = g % (kTileC / 16);
+        if (c0 + col * 16 >= nchans) continue;
+        uint32_t x = xs[n];
+        x = transpose_stage<16, 0x0000FFFFu>(x, lane);
+        x = transpose_stage<8, 0x00FF00FFu>(x, lane);
+        x = transpose_stage<4, 0x0F0F0F0Fu>(x, lane);
+        x = transpose_stage<2, 0x33333333u>(x, lane);
+        x = transpose_stage<1, 0x55555555u>(x, lane);
+        // lane k: plane k & 1 of channel col*16 + (k >> 1), word 2*sub + h
+        buf[(col * 16 + (k >> 1)) * kOutStride + 2 * (2 * sub + h) + (k & 1)] = x;
+    }
+    __syncthreads();
+
+    // 3. every channel row: 16 words = 128 contiguous bytes, two words per store
+    const int64_t j0 = t0 >> 5;
+    for (int r = tid; r < kTileC * (kTileW / 2); r += 256) {
+        const int cl = r / (kTileW / 2);
+        const int m = r % (kTileW / 2);
+        const int c = c0 + cl;
+        const int64_t j = j0 + 2 * m;
+        if (c >= nchans || j >= nwords) continue;
+        const uint32_t* src = buf + cl * kOutStride + 4 * m;
+        uint2* dst = words + static_cast<int64_t>(c) * nwords + j;
+        if (st16) {
+            *reinterpret_cast<uint4*>(dst) = make_uint4(src[0], src[1], src[2], src[3]);
+        } else {
+            dst[0] = make_uint2(src[0], src[1]);
+            dst[1] = make_uint2(src[2], src[3]);
         }
-        const int c = cbase + lane;
-        if (lane < 16 && c < nchans) {
-            uint2* dst = words + static_cast<int64_t>(c) * nwords + j;
-            dst[0] = make_uint2(static_cast<uint32_t>(mylo), static_cast<uint32_t>(myhi));
-            dst[1] = make_uint2(static_cast<uint32_t>(mylo >> 32), static_cast<uint32_t>(myhi >> 32));
-            if (j + 2 == nwords - 2) {   // last tile: clear the two trailing words
-                dst[2] = make_uint2(0u, 0u);
-                dst[3] = make_uint2(0u, 0u);
-            }
-        }
+    }
+    __syncthreads();   // the buffer is refilled by the next tile
     }
 }
 
@@ -83,14 +133,18 @@ __global__ __launch_bounds__(256) void repack_2bit_kernel(const uint8_t* __restr
 
 namespace dd {
 
+// Tiles cover the words, the two trailing ones included: every word of every
+// channel row is written once (zeros past the last sample).
 hipError_t launch_repack(const uint8_t* in, int64_t nsamps, int nchans, uint2* words,
                          int64_t nwords, hipStream_t s) {
-    const int64_t tiles_t = (nsamps + kTileT - 1) / kTileT;
-    if (nwords != 2 * tiles_t + 2) return hipErrorInvalidValue;
-    const dim3 grid(static_cast<unsigned>(tiles_t), static_cast<unsigned>((nchans + kTileC - 1) / kTileC));
+    if (nwords != repack_words(nsamps) || nwords % 2) return hipErrorInvalidValue;
+    const int64_t tiles_t = (nwords + kTileW - 1) / kTileW;
+    const dim3 grid(static_cast<unsigned>((nchans + kTileC - 1) / kTileC),
+                    static_cast<unsigned>(std::min<int64_t>(tiles_t, 65535)));
     const int vec16 = ((nchans >> 2) % 16 == 0) && (reinterpret_cast<uintptr_t>(in) % 16 == 0);
+    const int st16 = reinterpret_cast<uintptr_t>(words) % 16 == 0;
     hipLaunchKernelGGL(repack_2bit_kernel, grid, dim3(256), 0, s, in, nsamps, nchans, words,
-                       nwords, vec16);
+                       nwords, tiles_t, vec16, st16);
     return hipGetLastError();
 }
 
