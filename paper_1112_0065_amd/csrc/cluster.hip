@@ -383,12 +383,12 @@ size_t cluster_workspace_bytes(int64_t n, int32_t ndm, int32_t nwidths) {
     return cluster_layout(n, ndm, nwidths).bytes;
 }
 
-// Launch the whole stage; *total and *err (device) hold the cluster count
-// and the input-error flag when the stream reaches them.
+// Launch the whole stage.  *result (device) receives, when the stream reaches
+// it, two int64: the cluster count, then the input-error flag (low 32 bits).
 hipError_t launch_cluster(const dedisp_event* ev, int64_t n, int32_t ndm, const int32_t* widths,
                           int32_t nwidths, int32_t dm_radius, int32_t width_radius, int64_t time_tol,
                           dedisp_cluster* out, int64_t capacity, int32_t* labels, void* ws,
-                          int64_t** total, uint32_t** err, hipStream_t s) {
+                          const int64_t** result, hipStream_t s) {
     const ClusterLayout L = cluster_layout(n, ndm, nwidths);
     char* b = static_cast<char*>(ws);
     auto at = [&](size_t o) { return static_cast<void*>(b + o); };
@@ -405,8 +405,9 @@ hipError_t launch_cluster(const dedisp_event* ev, int64_t n, int32_t ndm, const 
     uint64_t* key = static_cast<uint64_t*>(at(L.o_key));
     int64_t* offs = static_cast<int64_t*>(at(L.o_offs));
     int64_t* chunk = static_cast<int64_t*>(at(L.o_chunk));
-    *total = static_cast<int64_t*>(at(L.o_total));
-    *err = static_cast<uint32_t*>(at(L.o_err));
+    int64_t* total = static_cast<int64_t*>(at(L.o_total));
+    uint32_t* err = static_cast<uint32_t*>(at(L.o_err));
+    *result = total;
 
     ClusterParams P{};
     P.ev = ev;
@@ -421,15 +422,15 @@ hipError_t launch_cluster(const dedisp_event* ev, int64_t n, int32_t ndm, const 
     const dim3 blk(kKThreads);
     const dim3 g_n(static_cast<unsigned>((n + kKThreads - 1) / kKThreads));
     const dim3 g_n1(static_cast<unsigned>((n + 1 + kKThreads - 1) / kKThreads));
-    hipLaunchKernelGGL(cluster_init_kernel, dim3(1), dim3(1), 0, s, *err);
-    hipLaunchKernelGGL(cluster_seg_kernel, g_n1, blk, 0, s, P, seg, parent, *err);
+    hipLaunchKernelGGL(cluster_init_kernel, dim3(1), dim3(1), 0, s, err);
+    hipLaunchKernelGGL(cluster_seg_kernel, g_n1, blk, 0, s, P, seg, parent, err);
     const int64_t nq = n * upper_series(dm_radius, width_radius);
     const int64_t link_blocks = std::min<int64_t>((nq + kKThreads - 1) / kKThreads, int64_t(1) << 20);
     hipLaunchKernelGGL(cluster_link_kernel, dim3(static_cast<unsigned>(link_blocks)), blk, 0, s, P,
                        seg, parent);
     hipLaunchKernelGGL(cluster_finish_kernel, g_n, blk, 0, s, n, parent, flag, cnt, dmlo, dmhi,
                        wlo, whi, tlo, thi, key);
-    hipError_t e = launch_scan_u32(flag, n, offs, chunk, *total, s);
+    hipError_t e = launch_scan_u32(flag, n, offs, chunk, total, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(cluster_accumulate_kernel,
                        dim3(static_cast<unsigned>((n + kAccEvents - 1) / kAccEvents)), blk, 0, s,
@@ -480,17 +481,14 @@ extern "C" dedisp_status dedisp_cluster_events(const dedisp_event* events, int64
         return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
     if (reinterpret_cast<uintptr_t>(workspace) % 256)
         return fail(DEDISP_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-    int64_t* d_total = nullptr;
-    uint32_t* d_err = nullptr;
+    const int64_t* d_result = nullptr;
     DD_HIP(dd::launch_cluster(events, n_events, ndm, widths, nwidths, dm_radius, width_radius,
-                              time_tol, clusters, capacity, labels, workspace, &d_total, &d_err,
-                              stream));
-    int64_t back[2] = {0, 0};   // count, error flag (adjacent in the workspace)
-    DD_HIP(hipMemcpyAsync(back, d_total, sizeof back, hipMemcpyDeviceToHost, stream));
+                              time_tol, clusters, capacity, labels, workspace, &d_result, stream));
+    int64_t back[2] = {0, 0};   // count, error flag
+    DD_HIP(hipMemcpyAsync(back, d_result, sizeof back, hipMemcpyDeviceToHost, stream));
     DD_HIP(hipStreamSynchronize(stream));
     const int64_t total = back[0];
     const uint32_t err = static_cast<uint32_t>(back[1]);
-    (void)d_err;
     if (err)
         return fail(DEDISP_ERR_INVALID_ARG,
                     "events are not in find_peaks order or have fields out of range");

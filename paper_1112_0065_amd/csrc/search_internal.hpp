@@ -65,7 +65,7 @@ size_t cluster_workspace_bytes(int64_t n, int32_t ndm, int32_t nwidths);
 hipError_t launch_cluster(const dedisp_event* ev, int64_t n, int32_t ndm, const int32_t* widths,
                           int32_t nwidths, int32_t dm_radius, int32_t width_radius, int64_t time_tol,
                           dedisp_cluster* out, int64_t capacity, int32_t* labels, void* ws,
-                          int64_t** total, uint32_t** err, hipStream_t s);
+                          const int64_t** result, hipStream_t s);
 hipError_t launch_baseline(const void* in, int in_u16, int ndm, int64_t nout, int radius,
                            int offset, void* out, int out_u16, hipStream_t s);
 hipError_t launch_boxcar(const void* in, int in_u16, int ndm, int64_t nout, const Widths& W,

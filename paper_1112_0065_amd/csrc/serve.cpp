@@ -284,15 +284,14 @@ void completer(dedisp_server_s* s) {
                 const Slot& sl = s->slots[j.slot];
                 int64_t nc = 0;
                 if (m > 0) {
-                    int64_t* d_total = nullptr;
-                    uint32_t* d_err = nullptr;
-                    int64_t back[2] = {0, 0};
+                    const int64_t* d_result = nullptr;
+                    int64_t back[2] = {0, 0};   // count, error flag
                     e = dd::launch_cluster(sl.d_events, m, s->plans[j.beam]->ndm, s->W.w, s->W.n,
                                            s->cl_dm_radius, s->cl_width_radius, s->cl_time_tol,
-                                           sl.d_clusters, s->capacity, nullptr, sl.cl_ws, &d_total,
-                                           &d_err, s->done_s);
+                                           sl.d_clusters, s->capacity, nullptr, sl.cl_ws, &d_result,
+                                           s->done_s);
                     if (e == hipSuccess)
-                        e = hipMemcpyAsync(back, d_total, sizeof back, hipMemcpyDeviceToHost, s->done_s);
+                        e = hipMemcpyAsync(back, d_result, sizeof back, hipMemcpyDeviceToHost, s->done_s);
                     if (e == hipSuccess) e = hipStreamSynchronize(s->done_s);
                     // find_peaks output always passes the input checks; a
                     // failed check leaves the chunk unclustered
