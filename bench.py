@@ -235,11 +235,22 @@ def main():
         bl_bytes = ndm * nout * 2 + ndm * (nout - 2 * R) * 2
         rec["baseline"] = {"radius": R, "ms": bl_ms, "algorithmic_bytes": bl_bytes,
                            "achieved_GBps": bl_bytes / (bl_ms * 1e-3) / 1e9,
-                           "hbm_frac": bl_bytes / (bl_ms * 1e-3) / 8e12}
+                           "hbm_frac": bl_bytes / (bl_ms * 1e-3) / 8e12,
+                           "output_samples_per_s": ndm * (nout - 2 * R) / (bl_ms * 1e-3)}
+        if not args.no_cpu_baseline:
+            import oracle
+            rows = out[:16].cpu().numpy().view(np.uint16).astype(np.int64)
+            t_c = time.perf_counter()
+            oracle.baseline_remove(rows, R, 3 * fb.nchans)
+            t_c = time.perf_counter() - t_c
+            rec["baseline"]["cpu_oracle"] = {
+                "value": 16 * (nout - 2 * R) / t_c, "unit": "output samples/s", "cores": 1,
+                "kind": "oracle", "sample": f"16 of {ndm} survey series ({t_c:.2f} s)"}
         del flat
-        rec["cluster"] = bench_cluster(evb, n_events, ndm, fb.widths)
+        rec["cluster"] = bench_cluster(evb, n_events, ndm, fb.widths, not args.no_cpu_baseline)
         rec["subband"] = bench_subband(fb, plan, inp, evb, n_events,
-                                       rec["stages_ms"]["repack"] + rec["stages_ms"]["dedisperse"])
+                                       rec["stages_ms"]["repack"] + rec["stages_ms"]["dedisperse"],
+                                       not args.no_cpu_baseline)
     del out, ws, pws, evb, inp
     torch.cuda.empty_cache()
     if not args.no_multibeam:
@@ -370,7 +381,7 @@ def bench_serve(args):
             "data": "4 fast-noise chunk payloads cycled over beams and sequence numbers"}
 
 
-def bench_subband(fb, plan, inp, evb, n_events, direct_ms):
+def bench_subband(fb, plan, inp, evb, n_events, direct_ms, cpu=False):
     """Subband dedispersion of the survey beam in place of the direct sum:
     time per beam (repack + both stages, HIP events on the stream; direct_ms
     is repack + direct dedispersion of the same beam), and what
@@ -426,13 +437,24 @@ def bench_subband(fb, plan, inp, evb, n_events, direct_ms):
             "speedup_vs_direct": direct_ms / ms, "events": n,
             "pulses_found_direct": int(found.sum()), "pulses_found": int((got[found] > 0).sum()),
             "snr_ratio_median": float(np.median(ratio)), "snr_ratio_min": float(ratio.min())}
+        if cpu and (nsub, group) == (16, 8):
+            import oracle
+            ns = sb.max_delay + 8192                     # 8192 output samples
+            x = oracle.unpack_2bit(fb.packed[:ns * fb.nchans // 4], ns, fb.nchans)
+            t_c = time.perf_counter()
+            oracle.subband_dedisperse(x, fb.f_top, fb.df, fb.tsamp, fb.dm_list, nsub, group)
+            t_c = time.perf_counter() - t_c
+            res[f"{nsub}x{group}"]["cpu_oracle"] = {
+                "value": ndm * 8192 / t_c, "unit": "DM-trial samples/s", "cores": 1,
+                "kind": "oracle", "sample": f"the first {ns} samples of the beam, 8192 outputs "
+                                            f"per trial ({t_c:.2f} s)"}
         del ws, out, pws, eb
         sb.close()
         torch.cuda.empty_cache()
     return res
 
 
-def bench_cluster(evb, n_events, ndm, widths):
+def bench_cluster(evb, n_events, ndm, widths, cpu=False):
     """Clustering of events across DM and width (friends of friends, DM
     radius 2, width radius 1, no time slack): the survey beam's own events,
     and a dense synthetic list of about a million events.  Each call includes
@@ -456,6 +478,16 @@ def bench_cluster(evb, n_events, ndm, widths):
         return {"events": n, "clusters": nc, "ms": dt * 1e3, "events_per_s": n / dt}
 
     res = {"survey_beam": run(evb, n_events, ndm, widths)}
+    if cpu:
+        import oracle
+        m = min(3000, n_events)
+        ev = L.events_from_buffer(evb, m)
+        t_c = time.perf_counter()
+        oracle.cluster_events(ev, widths, 2, 1, 0)
+        t_c = time.perf_counter() - t_c
+        res["cpu_oracle"] = {"value": m / t_c, "unit": "events/s", "cores": 1, "kind": "oracle",
+                             "sample": f"first {m} survey events ({t_c:.2f} s; all pairs tested, "
+                                       "so the rate falls as the list grows)"}
     ev = synth.make_event_list(77, 1200, 10, 1 << 22, nclumps=20000, nnoise=300000)
     buf = torch.from_numpy(np.frombuffer(ev.tobytes(), np.uint8).copy()).to("cuda")
     res["dense_synthetic"] = run(buf, len(ev), 1200, [1 << i for i in range(10)])
@@ -488,7 +520,18 @@ def bench_rfi_mask(args):
         n = L.dedisp_rfi_mask(ins, 1024, nsamps, 3.0, 4, mask, ws)
     dt = (time.perf_counter() - t0) / reps
     alg = nb * nsamps * (256 + 12) + nsamps
-    return {"beams": nb, "nsamps": nsamps, "ms": dt * 1e3, "masked": n,
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        ns = 1 << 14
+        t_c = time.perf_counter()
+        zs = [oracle.zero_dm_series(pool[:ns * 256], ns, 1024) for _ in range(nb)]
+        oracle.rfi_mask(zs, 3.0, 4)
+        t_c = time.perf_counter() - t_c
+        cpu = {"value": ns / t_c, "unit": "13-beam samples/s", "cores": 1, "kind": "oracle",
+               "sample": f"13 beams x {ns} samples ({t_c:.2f} s)"}
+    return {"beams": nb, "nsamps": nsamps, "ms": dt * 1e3, "masked": n, "cpu_oracle": cpu,
+            "samples_per_s": nsamps / dt,
             "algorithmic_bytes": alg, "achieved_GBps": alg / dt / 1e9,
             "hbm_frac": alg / dt / 8e12,
             "note": "includes the host synchronisation of the call; the same payload in every beam"}
