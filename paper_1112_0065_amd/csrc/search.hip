@@ -160,32 +160,102 @@ __global__ __launch_bounds__(kThreads) void boxcar_kernel(const T* __restrict__ 
     }
 }
 
-// Baseline (red-noise) removal by a running mean (paper section 2.3, first
-// paragraph): for output position t (input position t + R),
-//   out[t] = in[t + R] - floor((sum_{j=t}^{t+2R} in[j]) / (2R + 1)) + offset,
-// integer and exact; the running sum comes from the same LDS prefix scan as
-// the boxcars.  Grid (segments of Lb outputs, DMs).
+// Baseline (red-noise) removal by a running mean (section 2.3, first
+// paragraph), streamed: out[t] = s[t + R] - floor(W(t) / (2R + 1)) + offset,
+// W(t) = sum_{j=t}^{t+2R} s[j], integer and exact.  One wave walks kBlSeg
+// outputs of one row, 64 consecutive outputs per row of a step (lane l takes
+// t = tc + 64 i + l, so every load is coalesced).  The window slides:
+// W(t + 1) - W(t) = s[t + 2R + 1] - s[t], so W(t) is W(t0) plus an exclusive
+// wave prefix (DPP scan) of those differences -- one scan per row of 64
+// outputs, every sample loaded once by the front cursor (and again, from
+// cache, by the middle and back ones), no halo re-read.  Integers modulo 2^32
+// are exact as every window sum is below 2^31; the division is the
+// multiply-shift below.  The loads of the next step are in flight while a
+// step is computed.
+constexpr int kBlSeg = 16384;       // outputs per wave
+constexpr int kBlRows = 8;          // rows of 64 outputs per step
+constexpr int kBlStep = 64 * kBlRows;
+
+// Inclusive prefix sum over the 64 lanes of a wave: shifts within each row
+// of 16 lanes, then the row totals carried across rows.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x111, 0xF, 0xF, true));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x112, 0xF, 0xF, true));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x114, 0xF, 0xF, true));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x118, 0xF, 0xF, true));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x142, 0xA, 0xF, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x143, 0xC, 0xF, false));
+    return x;
+}
+
+template <typename T>
+__device__ __forceinline__ void bl_load(__amdgpu_buffer_rsrc_t rs, int64_t tc, int lane, int radius,
+                                        uint32_t (&b)[kBlRows], uint32_t (&f)[kBlRows],
+                                        uint32_t (&m)[kBlRows]) {
+    const int sz = static_cast<int>(sizeof(T));
+    const int base = static_cast<int>(tc) + lane;
+#pragma unroll
+    for (int i = 0; i < kBlRows; ++i) {
+        b[i] = row_load(rs, (base + 64 * i) * sz, static_cast<T*>(nullptr));
+        f[i] = row_load(rs, (base + 64 * i + 2 * radius + 1) * sz, static_cast<T*>(nullptr));
+        m[i] = row_load(rs, (base + 64 * i + radius) * sz, static_cast<T*>(nullptr));
+    }
+}
+
 template <typename T, typename U>
-__global__ __launch_bounds__(kThreads) void baseline_kernel(const T* __restrict__ in, int64_t nout,
-                                                            int64_t nres, int radius, int offset,
-                                                            int Lb, uint64_t magic, int shift,
-                                                            U* __restrict__ out) {
-    extern __shared__ uint32_t pl[];
-    __shared__ uint32_t wave_tot[kThreads / 64];
-    const int d = blockIdx.y;
-    const int64_t s0 = static_cast<int64_t>(blockIdx.x) * Lb;
+__global__ __launch_bounds__(kThreads) void baseline_kernel(const T* __restrict__ in, int ndm,
+                                                            int64_t nout, int64_t nres, int radius,
+                                                            int offset, int64_t nseg, uint64_t magic,
+                                                            int shift, U* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t item = (static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x) >> 6;
+    if (item >= static_cast<int64_t>(ndm) * nseg) return;   // whole waves
+    const int d = static_cast<int>(item / nseg);
+    const int64_t t0 = (item % nseg) * kBlSeg;
+    const int64_t t1 = min<int64_t>(t0 + kBlSeg, nres);
+    const T* row = in + static_cast<int64_t>(d) * nout;
+    // a row stays below 2^31 bytes; offsets past it read as 0
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<T*>(row), 0, static_cast<int>(nout * static_cast<int64_t>(sizeof(T))), kRowRsrcWord3);
+    const int sz = static_cast<int>(sizeof(T));
     const int win = 2 * radius + 1;
-    const int n = Lb + win;   // running sums pl[0..n)
-    load_prefix(in + static_cast<int64_t>(d) * nout, nout, s0, n, pl, wave_tot);
+    // front start: the sum of s[t0 .. t0 + 2R]
+    uint32_t acc = 0;
+    for (int base = static_cast<int>(t0) + lane; base < static_cast<int>(t0) + win; base += kBatch * 64) {
+        uint32_t v[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const int i = base + k * 64;
+            v[k] = i < static_cast<int>(t0) + win ? row_load(rs, i * sz, static_cast<T*>(nullptr)) : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) acc += v[k];
+    }
+    // W(t0): the sum of s[t0 .. t0 + 2R]
+    uint32_t wcur = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(wave_incl_scan(acc)), 63));
     U* o = out + static_cast<int64_t>(d) * nres;
-    for (int i = threadIdx.x; i < Lb; i += kThreads) {
-        const int64_t t = s0 + i;
-        if (t >= nres) break;
-        const uint32_t sum = pl[i + win] - pl[i];
-        const uint32_t x = pl[i + radius + 1] - pl[i + radius];
-        // floor(sum / win) as a multiply and shift (exact for sum < 2^31)
-        const uint32_t mean = static_cast<uint32_t>((static_cast<uint64_t>(sum) * magic) >> shift);
-        o[t] = static_cast<U>(static_cast<int32_t>(x) - static_cast<int32_t>(mean) + offset);
+    uint32_t b[kBlRows], f[kBlRows], m[kBlRows];
+    bl_load<T>(rs, t0, lane, radius, b, f, m);
+    for (int64_t tc = t0; tc < t1; tc += kBlStep) {
+        uint32_t nb[kBlRows], nf[kBlRows], nm[kBlRows];
+        bl_load<T>(rs, tc + kBlStep, lane, radius, nb, nf, nm);   // next step, in flight
+#pragma unroll
+        for (int i = 0; i < kBlRows; ++i) {
+            const uint32_t delta = f[i] - b[i];        // W(t + 1) - W(t)
+            const uint32_t incl = wave_incl_scan(delta);
+            const uint32_t sum = wcur + incl - delta;   // W(t)
+            // floor(sum / win) as a multiply and shift (exact for sum < 2^31)
+            const uint32_t mean = static_cast<uint32_t>((static_cast<uint64_t>(sum) * magic) >> shift);
+            const int64_t t = tc + 64 * i + lane;
+            if (t < t1) o[t] = static_cast<U>(static_cast<int32_t>(m[i]) - static_cast<int32_t>(mean) + offset);
+            wcur += static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(incl), 63));
+        }
+#pragma unroll
+        for (int i = 0; i < kBlRows; ++i) {
+            b[i] = nb[i];
+            f[i] = nf[i];
+            m[i] = nm[i];
+        }
     }
 }
 
@@ -880,7 +950,6 @@ hipError_t launch_boxcar(const void* in, int in_u16, int ndm, int64_t nout, cons
 hipError_t launch_baseline(const void* in, int in_u16, int ndm, int64_t nout, int radius,
                            int offset, void* out, int out_u16, hipStream_t s) {
     const int64_t nres = nout - 2 * static_cast<int64_t>(radius);
-    const int Lb = 8192;
     // floor(n / w) = (n * M) >> k with k = 31 + ceil(log2 w), M = ceil(2^k / w):
     // writing M w = 2^k + e (0 <= e < w), n M / 2^k = n / w + n e / (w 2^k), and
     // n e < 2^31 * 2^ceil(log2 w) = 2^k for n < 2^31, so the extra term stays
@@ -890,16 +959,13 @@ hipError_t launch_baseline(const void* in, int in_u16, int ndm, int64_t nout, in
     while ((1u << lg) < win) ++lg;
     const int shift = 31 + lg;
     const uint64_t magic = ((uint64_t(1) << shift) + win - 1) / win;
-    const size_t lds = static_cast<size_t>(Lb + 2 * radius + 1) * 4;
-    const dim3 grid(static_cast<unsigned>((nres + Lb - 1) / Lb), static_cast<unsigned>(ndm));
+    const int64_t nseg = (nres + kBlSeg - 1) / kBlSeg;
+    const int64_t waves = static_cast<int64_t>(ndm) * nseg;
+    const dim3 grid(static_cast<unsigned>((waves + kThreads / 64 - 1) / (kThreads / 64)));
 #define DD_BL(T, U)                                                                            \
-    {                                                                                          \
-        hipError_t e = set_lds_limit(reinterpret_cast<const void*>(baseline_kernel<T, U>), lds); \
-        if (e != hipSuccess) return e;                                                         \
-        hipLaunchKernelGGL((baseline_kernel<T, U>), grid, dim3(kThreads), lds, s,              \
-                           static_cast<const T*>(in), nout, nres, radius, offset, Lb, magic,   \
-                           shift, static_cast<U*>(out));                                       \
-    }
+    hipLaunchKernelGGL((baseline_kernel<T, U>), grid, dim3(kThreads), 0, s,                     \
+                       static_cast<const T*>(in), ndm, nout, nres, radius, offset, nseg, magic, \
+                       shift, static_cast<U*>(out));
     if (in_u16 && out_u16) DD_BL(uint16_t, uint16_t)
     else if (in_u16) DD_BL(uint16_t, int32_t)
     else if (out_u16) DD_BL(int32_t, uint16_t)
