@@ -42,7 +42,7 @@ PEAK_LDS_ADDS = 256 * 2.4e9 * 128 / 16 * 32
 # packed adds): what a kernel adding unpacked samples could reach at most.
 PEAK_PK16_ADDS = 256 * 64 * 2 * 2.4e9
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dedisperse_survey_traffic.json")
-KERNEL_SOURCES = ["dedisperse.hip", "bitslice.hpp", "csa_tree.inc", "repack.hip"]
+KERNEL_SOURCES = ["dedisperse.hip", "bitslice.hpp", "csa_tree.inc", "dedisp_internal.hpp"]
 
 
 def kernel_hash():

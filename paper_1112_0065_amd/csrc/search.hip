@@ -334,7 +334,7 @@ __device__ __forceinline__ void stats_full_nw(uint32_t* pl, const dd::Widths& W,
         woff[wi] = W.w[wi];
     }
     const uint32_t* base = pl + 1 + threadIdx.x;
-#pragma unroll 4
+#pragma unroll 8
     for (int j = 0; j < kPerThread; ++j) {
         const uint32_t p0 = base[j * kThreads];
 #pragma unroll
