@@ -50,6 +50,7 @@ struct BeamArgs {
     int n_dm_blocks;
     int tile_words;          // T/32 + 1 of the launch's tile shape
     int pitch;               // words per LDS row: tile_words + the largest block skew
+    int dm_group;            // DM blocks per group of the work-item order
     int64_t item_begin;      // first work item of this beam in a batch
     int64_t n_items;         // time tiles x DM blocks
 };

@@ -19,6 +19,8 @@
 //   * after the last stage the counter planes are transposed to integers in
 //     registers and written once (int32 or uint16).
 // The result is exact; its order of additions is irrelevant (integers).
+#include <algorithm>
+
 #include "bitslice.hpp"
 #include "dedisp_internal.hpp"
 
@@ -26,6 +28,9 @@ namespace {
 
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
+// L2 bytes of delay and offset rows that one group of DM blocks may occupy
+// (an XCD has 4 MiB of L2, shared with the input windows).
+constexpr int64_t kItemGroupBytes = int64_t(2) << 20;
 
 // Read-only tables (delays, skews, beam descriptors) are read through the
 // constant address space: the loads stay scalar even after the output stores
@@ -247,6 +252,21 @@ __device__ __forceinline__ void process_item(const dd::BeamArgs& a, int tile, in
     }
 }
 
+// Work items go in groups of a.dm_group DM blocks: inside a group the DM
+// block varies fastest, then the time tile.  The group's delay and offset rows
+// then stay in L2 while its time tiles go by, and the DM blocks of one time
+// tile, whose input windows overlap, run together.
+__device__ __forceinline__ void item_coords(const dd::BeamArgs& a, int64_t item, int* tile,
+                                            int* dblk) {
+    const int64_t n_tt = a.n_items / a.n_dm_blocks;
+    const int64_t per_group = static_cast<int64_t>(a.dm_group) * n_tt;
+    const int g = static_cast<int>(item / per_group);
+    const int64_t rem = item - g * per_group;
+    const int gs = min(a.dm_group, a.n_dm_blocks - g * a.dm_group);
+    *tile = static_cast<int>(rem / gs);
+    *dblk = g * a.dm_group + static_cast<int>(rem % gs);
+}
+
 template <int NL, int NDW, int G, bool OUT16>
 __global__ __launch_bounds__(kThreads) void dedisperse_kernel(dd::BeamArgs a, int stage_chans,
                                                               int n_items) {
@@ -260,8 +280,9 @@ __global__ __launch_bounds__(kThreads) void dedisperse_kernel(dd::BeamArgs a, in
     const int per_xcd = gridDim.x / 8;
     const int item = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (item >= n_items) return;
-    process_item<NL, NDW, G, OUT16>(a, item / a.n_dm_blocks, item % a.n_dm_blocks, stage_chans,
-                                    lds, lane, wave);
+    int tile, dblk;
+    item_coords(a, item, &tile, &dblk);
+    process_item<NL, NDW, G, OUT16>(a, tile, dblk, stage_chans, lds, lane, wave);
 }
 
 // Persistent form over the work items of several beams: blocks pop items
@@ -296,9 +317,9 @@ __global__ __launch_bounds__(kThreads) void dedisperse_persistent_kernel(
         while (b + 1 < nbeams && item >= cb[b + 1].item_begin) ++b;
         const dd::BeamArgs a = load_beam(cb + b);
         const int64_t local = item - a.item_begin;
-        process_item<NL, NDW, G, OUT16>(a, static_cast<int>(local / a.n_dm_blocks),
-                                        static_cast<int>(local % a.n_dm_blocks), stage_chans, lds,
-                                        lane, wave);
+        int tile, dblk;
+        item_coords(a, local, &tile, &dblk);
+        process_item<NL, NDW, G, OUT16>(a, tile, dblk, stage_chans, lds, lane, wave);
     }
 }
 
@@ -380,6 +401,10 @@ BeamArgs beam_args(const dedisp_plan_s* p, const uint2* words, int64_t nwords, i
     a.skew = k >= 0 ? p->d_skew[k] : nullptr;
     a.out = out;
     a.n_dm_blocks = (p->ndm + cfg.dms_per_block - 1) / cfg.dms_per_block;
+    // groups whose delay and offset rows (8 bytes per trial and channel) fill
+    // about kItemGroupBytes of L2
+    const int64_t rows = static_cast<int64_t>(cfg.dms_per_block) * p->nchans * 8;
+    a.dm_group = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(a.n_dm_blocks, kItemGroupBytes / rows)));
     const int64_t T = 2048 * cfg.groups;
     a.tile_words = static_cast<int>(T / 32 + 1);
     a.pitch = tile_pitch(p, cfg);
