@@ -488,35 +488,63 @@ __global__ __launch_bounds__(kThreads) void boxcar_stats_kernel(const T* __restr
     }
 }
 
-// Pass 2: one thread per (width, DM) series: exact sums, D and B_thr.
+// Pass 2: exact sums, D and B_thr per (width, DM) series, kSerPerBlock
+// series per block.  A series' partials are contiguous (series-major), so the
+// block stages a chunk of segments of all its series in LDS with loads that
+// every thread issues at once (one memory round trip per chunk); thread t then
+// adds series t's entries.  The sums are exact integers: their order is free.
+constexpr int kSerPerBlock = 64;
+constexpr int kSerChunk = 32;   // segments per staged chunk: 3 x 64 x 32 x 8 B = 48 KiB
 __global__ __launch_bounds__(kThreads) void series_threshold_kernel(int nseries, int nseg,
                                                                     int64_t nbx, uint32_t kmant,
                                                                     int kexp2, dd::PeaksWs ws) {
-    const int s = blockIdx.x * kThreads + threadIdx.x;
-    if (s == 0) {
+    __shared__ uint64_t st1[kSerPerBlock * kSerChunk];
+    __shared__ uint64_t st2lo[kSerPerBlock * kSerChunk];
+    __shared__ uint64_t st2hi[kSerPerBlock * kSerChunk];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         ws.nlist[0] = 0u;   // the mark and count passes append to the work lists
         ws.nlist[1] = 0u;
     }
-    if (s >= nseries) return;
+    const int s0 = blockIdx.x * kSerPerBlock;
+    const int ns = min(kSerPerBlock, nseries - s0);
+    const int t = threadIdx.x;
     uint64_t s1 = 0;
     u128 s2 = 0;
-    // partials in batches of 8 loads (independent, so their latencies overlap)
-    for (int g0 = 0; g0 < nseg; g0 += 8) {
-        uint64_t p1[8], plo[8], phi[8];
+    for (int c0 = 0; c0 < nseg; c0 += kSerChunk) {
+        const int nc = min(kSerChunk, nseg - c0);
+        const int n = ns * nc;
+        constexpr int kPer = kSerPerBlock * kSerChunk / kThreads;
+        uint64_t v1[kPer], vlo[kPer], vhi[kPer];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int64_t idx = static_cast<int64_t>(s) * nseg + g0 + k;
-            const bool in = g0 + k < nseg;
-            p1[k] = in ? ws.part_s1[idx] : 0;
-            plo[k] = in ? ws.part_s2lo[idx] : 0;
-            phi[k] = in ? ws.part_s2hi[idx] : 0;
+        for (int k = 0; k < kPer; ++k) {
+            const int i = t + k * kThreads;
+            const int64_t idx = static_cast<int64_t>(s0 + i / nc) * nseg + c0 + i % nc;
+            const bool in = i < n;
+            v1[k] = in ? ws.part_s1[idx] : 0;
+            vlo[k] = in ? ws.part_s2lo[idx] : 0;
+            vhi[k] = in ? ws.part_s2hi[idx] : 0;
         }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            s1 += p1[k];
-            s2 += static_cast<u128>(plo[k]) | (static_cast<u128>(phi[k]) << 64);
+        for (int k = 0; k < kPer; ++k) {
+            const int i = t + k * kThreads;
+            if (i < n) {
+                st1[i] = v1[k];
+                st2lo[i] = vlo[k];
+                st2hi[i] = vhi[k];
+            }
         }
+        __syncthreads();
+        if (t < ns) {
+            for (int k = 0; k < nc; ++k) {
+                const int i = t * nc + k;
+                s1 += st1[i];
+                s2 += static_cast<u128>(st2lo[i]) | (static_cast<u128>(st2hi[i]) << 64);
+            }
+        }
+        __syncthreads();   // the next chunk overwrites the staging arrays
     }
+    if (t >= ns) return;
+    const int s = s0 + t;
     ws.s1[s] = s1;
     ws.s2lo[s] = static_cast<uint64_t>(s2);
     ws.s2hi[s] = static_cast<uint64_t>(s2 >> 64);
@@ -1090,7 +1118,7 @@ hipError_t launch_peaks_count(const void* in, int in_u16, int ndm, int64_t nout,
     hipError_t e = launch_stats(in, in_u16, nout, W, lay, ws, grid, lds, s);
     if (e != hipSuccess) return e;
     const int nser = static_cast<int>(lay.nseries);
-    hipLaunchKernelGGL(series_threshold_kernel, dim3((nser + kThreads - 1) / kThreads), dim3(kThreads),
+    hipLaunchKernelGGL(series_threshold_kernel, dim3((nser + kSerPerBlock - 1) / kSerPerBlock), dim3(kThreads),
                        0, s, nser, lay.nseg, lay.nbx, kmant, kexp2, ws);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
