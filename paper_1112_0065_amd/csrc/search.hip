@@ -771,6 +771,72 @@ __device__ __forceinline__ void write_event(const T* __restrict__ row, int64_t n
     *out = ev;
 }
 
+// The same walk done by a whole wave, 64 consecutive positions per step.
+// Inside the LDS window a lane takes its position's boxcar from the running
+// sums; beyond it, the boxcars follow from the last one by a wave prefix sum
+// of the add/subtract pairs.  The run goes on through the lanes before the
+// first one whose boxcar is below the cut (a ballot); the peak is the largest
+// boxcar, the earliest on ties, as in the walk above, so both give the same
+// event.  Arguments are uniform over the wave; lane 0 writes the event.
+template <typename T>
+__device__ __forceinline__ void write_event_wave(const T* __restrict__ row, int64_t nbx, int w, int wi,
+                                                 int d, int64_t t, uint32_t b, uint32_t thr, uint64_t s1,
+                                                 double sqrt_d, dedisp_event* __restrict__ out,
+                                                 const uint32_t* pl, int64_t s0, int lim, int lane) {
+    int64_t te = t, tp = t;
+    uint32_t cur = b, best = b;
+    bool open = true;
+    int64_t u = t;   // last position of the run so far
+    while (open && u + 1 < nbx) {
+        const int64_t v = u + 1 + lane;
+        bool valid;
+        uint32_t bb = 0u;
+        if (u + 1 - s0 < lim) {
+            // validity falls from true to false at most once along the lanes
+            valid = v < nbx && v - s0 < lim;
+            if (valid) {
+                const int j = static_cast<int>(v - s0);
+                bb = pl[j + 1 + w] - pl[j + 1];
+            }
+        } else {
+            valid = v < nbx;   // then u + lane + w <= nout - 1
+            const uint32_t delta =
+                valid ? static_cast<uint32_t>(row[u + lane + w]) - static_cast<uint32_t>(row[u + lane]) : 0u;
+            bb = cur + wave_incl_scan(delta);
+        }
+        const uint64_t below = __ballot(valid && bb < thr);
+        const uint64_t stop = below | __ballot(!valid);
+        const int nlive = stop ? __builtin_ctzll(stop) : 64;
+        if (nlive > 0) {
+            uint32_t m = lane < nlive ? bb : 0u;
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) m = max(m, static_cast<uint32_t>(__shfl_xor(m, o, 64)));
+            if (m > best) {
+                best = m;
+                tp = u + 1 + __builtin_ctzll(__ballot(lane < nlive && bb == m));
+            }
+            cur = static_cast<uint32_t>(__shfl(bb, nlive - 1, 64));
+            te = u + nlive;
+        }
+        // the run ends at a position below the cut; leaving the window or the
+        // data does not end it
+        if (nlive < 64 && ((below >> nlive) & 1u)) open = false;
+        u += nlive;
+    }
+    if (lane == 0) {
+        const int64_t lval = static_cast<int64_t>(nbx) * best - static_cast<int64_t>(s1);
+        dedisp_event ev;
+        ev.width_idx = wi;
+        ev.dm_idx = d;
+        ev.t_start = t;
+        ev.t_end = te;
+        ev.t_peak = tp;
+        ev.b_peak = static_cast<int32_t>(best);
+        ev.snr = static_cast<float>(static_cast<double>(lval) / sqrt_d);
+        *out = ev;
+    }
+}
+
 // Pass 4: write the events of segments that have any.  The run starts of a
 // (width, DM, segment) are collected in LDS (any order), ranked by position
 // (they are few), and each is expanded by one thread at offset + rank;
@@ -837,19 +903,23 @@ __device__ __forceinline__ void write_segment(const T* __restrict__ in, int ndm,
             }
         }
         __syncthreads();
-        for (uint32_t k = threadIdx.x; k < total; k += kThreads) {
+        // one run per wave: its rank among its width's starts, then its walk
+        const int lane = threadIdx.x & 63;
+        for (uint32_t k = threadIdx.x >> 6; k < total; k += kThreads / 64) {
             int wi = 0;
             while (wb[wi + 1] <= k) ++wi;
             const int i = starts[k];
             uint32_t rank = 0;
-            for (uint32_t q = wb[wi]; q < wb[wi + 1]; ++q) rank += starts[q] < i;
+            for (uint32_t q = wb[wi] + lane; q < wb[wi + 1]; q += 64) rank += starts[q] < i;
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) rank += __shfl_xor(rank, o, 64);
             const int64_t cidx = (static_cast<int64_t>(wi) * ndm + d) * nseg + seg;
             const int64_t e = ws.offs[cidx] + rank;
             const int w = W.w[wi];
             const int sidx = wi * ndm + d;
             if (e < capacity)
-                write_event(row, nbx, w, wi, d, s0 + i, pl[i + 1 + w] - pl[i + 1], wthr[wi], ws.s1[sidx],
-                            ws.sqrt_d[sidx], &events[e], pl, s0, n - 1 - w);
+                write_event_wave(row, nbx, w, wi, d, s0 + i, pl[i + 1 + w] - pl[i + 1], wthr[wi],
+                                 ws.s1[sidx], ws.sqrt_d[sidx], &events[e], pl, s0, n - 1 - w, lane);
         }
         return;
     }

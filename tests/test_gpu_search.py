@@ -104,6 +104,36 @@ def test_find_peaks_thresholds_and_ties(k):
         events_equal(ev, ref)
 
 
+@pytest.mark.parametrize("k", [1.0, 2.0])
+def test_find_peaks_runs_leave_the_segment_window(k):
+    """Runs that start in one 8192-position segment and go on past its
+    running-sum window (so their walk continues on the series in global
+    memory, over several 64-position steps): a long run across a segment
+    boundary, a run whose peak lies beyond the window, a plateau (the peak is
+    its first position), and a run that reaches the end of the data."""
+    rng = np.random.default_rng(5)
+    series = rng.integers(0, 12, size=(5, 40000)).astype(np.int64)
+    series[0, 8000:9600] = 60
+    series[1, 16000:16500] = 50
+    series[1, 16400:16450] = 80
+    series[2, 30000:] = 40
+    series[3, 8100:8192 + 64 * 3] = 45
+    series[4, 24500:24576 + 200] = 30
+    series[4, 24576 + 100:24576 + 130] = 90
+    widths = [1, 4, 64]
+    bw = oracle.boxcar(series, widths)
+    ref = oracle.find_events(bw, k)
+    seg = 8192
+    crossing = [e for e in ref if e[3] >= (e[2] // seg + 1) * seg + widths[-1] - widths[e[0]]]
+    assert len(crossing) >= 12
+    s1, s2, thr = _ref_stats(bw, k)
+    for u16 in (False, True):
+        log("find_peaks window-crossing runs k", k, "u16", u16, "ref events", len(ref))
+        ev, (g1, g2, gt) = _find(series, widths, k, u16)
+        assert (g1 == s1).all() and (g2 == s2).all() and (gt == thr).all()
+        events_equal(ev, ref)
+
+
 def test_find_peaks_capacity_overflow():
     from paper_1112_0065_amd import _lib as L
     rng = np.random.default_rng(3)
