@@ -78,7 +78,22 @@ __device__ void load_prefix(const T* __restrict__ row, int64_t nout, int64_t fir
         const_cast<T*>(row), 0, static_cast<int>(nout * static_cast<int64_t>(sizeof(T))), kRowRsrcWord3);
     const int off0 = static_cast<int>(first) * static_cast<int>(sizeof(T));
     uint32_t m = 0;
-    for (int base = threadIdx.x; base < n - 1; base += kBatch * kThreads) {
+    // full batches (every index below n - 1) store without checks; the last,
+    // partial one checks each index
+    int base = threadIdx.x;
+    for (; base + (kBatch - 1) * kThreads < n - 1; base += kBatch * kThreads) {
+        uint32_t v[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k)
+            v[k] = row_load(rs, off0 + (base + k * kThreads) * static_cast<int>(sizeof(T)),
+                            static_cast<T*>(nullptr));
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            pl[base + k * kThreads + 1] = v[k];
+            m = max(m, v[k]);
+        }
+    }
+    if (base < n - 1) {
         uint32_t v[kBatch];
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
@@ -104,24 +119,43 @@ __device__ void load_prefix(const T* __restrict__ row, int64_t nout, int64_t fir
     const int chunk = (((n - 1) + kThreads - 1) / kThreads) | 1;
     const int lo = 1 + threadIdx.x * chunk;
     const int hi = min(n, lo + chunk);
+    // full batches without checks, then one checked remainder batch
+    const int full_end = lo + ((max(hi - lo, 0)) / kBatch) * kBatch;
     uint32_t sum = 0;
-    for (int i0 = lo; i0 < hi; i0 += kBatch) {
+    for (int i0 = lo; i0 < full_end; i0 += kBatch) {
         uint32_t v[kBatch];
 #pragma unroll
-        for (int k = 0; k < kBatch; ++k) v[k] = i0 + k < hi ? pl[i0 + k] : 0u;
+        for (int k = 0; k < kBatch; ++k) v[k] = pl[i0 + k];
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) sum += v[k];
     }
-    const uint32_t base = block_exclusive_scan(sum, wave_tot);
-    uint32_t run = base;
-    for (int i0 = lo; i0 < hi; i0 += kBatch) {
+    if (full_end < hi) {
         uint32_t v[kBatch];
 #pragma unroll
-        for (int k = 0; k < kBatch; ++k) v[k] = i0 + k < hi ? pl[i0 + k] : 0u;
+        for (int k = 0; k < kBatch; ++k) v[k] = full_end + k < hi ? pl[full_end + k] : 0u;
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) sum += v[k];
+    }
+    const uint32_t scan_base = block_exclusive_scan(sum, wave_tot);
+    uint32_t run = scan_base;
+    for (int i0 = lo; i0 < full_end; i0 += kBatch) {
+        uint32_t v[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) v[k] = pl[i0 + k];
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
             run += v[k];
-            if (i0 + k < hi) pl[i0 + k] = run;
+            pl[i0 + k] = run;
+        }
+    }
+    if (full_end < hi) {
+        uint32_t v[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) v[k] = full_end + k < hi ? pl[full_end + k] : 0u;
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            run += v[k];
+            if (full_end + k < hi) pl[full_end + k] = run;
         }
     }
     if (threadIdx.x == 0) pl[0] = 0u;
