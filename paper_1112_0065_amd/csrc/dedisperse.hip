@@ -28,9 +28,10 @@ namespace {
 
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
-// L2 bytes of delay and offset rows that one group of DM blocks may occupy
-// (an XCD has 4 MiB of L2, shared with the input windows).
-constexpr int64_t kItemGroupBytes = int64_t(2) << 20;
+// L2 bytes of LDS-offset rows that one group of DM blocks may occupy: a
+// quarter of an XCD's 4 MiB L2, the rest holding the input windows and the
+// blocks' delay rows (one row per block).
+constexpr int64_t kItemGroupBytes = int64_t(1) << 20;
 
 // Read-only tables (delays, skews, beam descriptors) are read through the
 // constant address space: the loads stay scalar even after the output stores
@@ -253,9 +254,9 @@ __device__ __forceinline__ void process_item(const dd::BeamArgs& a, int tile, in
 }
 
 // Work items go in groups of a.dm_group DM blocks: inside a group the DM
-// block varies fastest, then the time tile.  The group's delay and offset rows
-// then stay in L2 while its time tiles go by, and the DM blocks of one time
-// tile, whose input windows overlap, run together.
+// block varies fastest, then the time tile.  The group's offset rows then stay
+// in L2 while its time tiles go by, and the DM blocks of one time tile, whose
+// input windows overlap, run together.
 __device__ __forceinline__ void item_coords(const dd::BeamArgs& a, int64_t item, int* tile,
                                             int* dblk) {
     const int64_t n_tt = a.n_items / a.n_dm_blocks;
@@ -401,9 +402,9 @@ BeamArgs beam_args(const dedisp_plan_s* p, const uint2* words, int64_t nwords, i
     a.skew = k >= 0 ? p->d_skew[k] : nullptr;
     a.out = out;
     a.n_dm_blocks = (p->ndm + cfg.dms_per_block - 1) / cfg.dms_per_block;
-    // groups whose delay and offset rows (8 bytes per trial and channel) fill
-    // about kItemGroupBytes of L2
-    const int64_t rows = static_cast<int64_t>(cfg.dms_per_block) * p->nchans * 8;
+    // groups whose LDS-offset rows (4 bytes per trial and channel) fill about
+    // kItemGroupBytes of L2
+    const int64_t rows = static_cast<int64_t>(cfg.dms_per_block) * p->nchans * 4;
     a.dm_group = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(a.n_dm_blocks, kItemGroupBytes / rows)));
     const int64_t T = 2048 * cfg.groups;
     a.tile_words = static_cast<int>(T / 32 + 1);
