@@ -119,3 +119,15 @@ def test_baseline_division_by_multiply_is_exact():
                 [rnd.randrange(1 << 31) for _ in range(20)]:
             assert (n * m) >> k == n // w
             assert n * m < (1 << 63)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asked for more it says so and exits
+    before touching a device."""
+    import sys
+    for args, env in ((["--gpus", "2"], {}), (["--gpus", "8"], {}), ([], {"WORLD_SIZE": "4"})):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args],
+                           capture_output=True, text=True, timeout=60,
+                           env={**os.environ, **env})
+        assert r.returncode == 2, (args, env, r.stderr)
+        assert "exactly one GPU" in r.stderr and r.stdout == ""
