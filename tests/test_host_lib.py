@@ -23,6 +23,20 @@ def test_library_exports_every_declared_symbol():
     assert L.dedisp_version().decode().startswith("dedisp-gfx950")
 
 
+def test_every_exported_c_symbol_is_declared():
+    """The converse: no unmangled symbol leaves the library without a
+    declaration in the header."""
+    import shutil
+    from paper_1112_0065_amd import _lib
+    if shutil.which("nm") is None:
+        pytest.skip("nm not available")
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {f[2] for f in (line.split() for line in out.splitlines())
+                if len(f) == 3 and f[1] == "T" and not f[2].startswith("_")}
+    assert exported == set(_lib.declared_symbols())
+
+
 def test_tile_candidates_host_only():
     from paper_1112_0065_amd import _lib
     tiles = _lib.dedisp_tile_candidates()
