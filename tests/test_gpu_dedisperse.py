@@ -100,6 +100,27 @@ def test_tiny_and_edge_shapes(nchans, nsamps, dms, seed):
             assert (got == ref).all(), (nchans, dtype, tile)
 
 
+def test_grouped_item_order_whole_output():
+    """4096 channels x 200 trials: the work items go in several groups of DM
+    blocks with a shorter last group (16 trials per block: groups of 4, 4, 4
+    and 1 blocks; 32: 2, 2, 2, 1; 8: 8, 8, 8, 1) over three time tiles, the
+    last one ragged.  The whole output equals the oracle's."""
+    torch = torch_dev()
+    from paper_1112_0065_amd import _lib as L
+    nchans = 4096
+    dms = list(np.linspace(0.0, 30.0, 200))
+    df = -400.0 / nchans
+    dly = oracle.delay_table(nchans, synth.F_TOP, df, synth.TSAMP, dms)
+    nsamps = int(dly.max()) + 5000
+    fb = synth.make_tiny(9, nchans, nsamps, dms, df=df)
+    p = L.dedisp_plan_create(nchans, fb.f_top, df, fb.tsamp, dms)
+    ref = oracle.dedisperse(oracle.unpack_2bit(fb.packed, nsamps, nchans), dly)
+    for tile in [None, (32, 1, 16), (8, 1, 16)]:
+        log("grouped items 4096 ch x 200 trials, tile", tile)
+        got = _run(p, fb.packed, nsamps, torch.int32, tile)
+        assert got.shape == ref.shape and (got == ref).all(), tile
+
+
 @pytest.mark.parametrize("extra", [1, 2, 31, 32, 33, 2047, 2048, 2049, 4095, 4097])
 def test_ragged_output_lengths(extra):
     """nout just around multiples of the 32-sample group and the time tile."""
