@@ -85,8 +85,18 @@ __device__ __forceinline__ u256 u256_add(u256 a, const u256& b) {
     return a;
 }
 
-// floor(sqrt(x)), digit-by-digit (binary restoring method).
+// floor(sqrt(x)).  Below 2^104 the root is under 2^52: a double square root
+// lands within a few units of it, and exact 128-bit squares step it to the
+// floor.  Otherwise digit by digit (binary restoring method).
 __device__ u256 u256_isqrt(u256 x) {
+    if ((x.w[3] | x.w[2]) == 0 && (x.w[1] >> 40) == 0) {
+        const u128 xx = static_cast<u128>(x.w[1]) << 64 | x.w[0];
+        const double xd = static_cast<double>(x.w[1]) * 18446744073709551616.0 + static_cast<double>(x.w[0]);
+        uint64_t r = static_cast<uint64_t>(sqrt(xd));
+        while (r > 0 && static_cast<u128>(r) * r > xx) --r;
+        while (static_cast<u128>(r + 1) * (r + 1) <= xx) ++r;
+        return u256{{r, 0, 0, 0}};
+    }
     u256 res{{0, 0, 0, 0}};
     u256 bit{{0, 0, 0, 0}};
     // highest power of four <= x
@@ -109,8 +119,10 @@ __device__ u256 u256_isqrt(u256 x) {
     return res;
 }
 
-// floor(a / b), a < 2^128, b >= 1 (shift-subtract).
+// floor(a / b), a < 2^128, b >= 1: one 64-bit division when a fits 64 bits,
+// else shift-subtract.
 __device__ u128 u128_div_u64(u128 a, uint64_t b) {
+    if ((a >> 64) == 0) return static_cast<uint64_t>(a) / b;
     u128 q = 0, r = 0;
     for (int i = 127; i >= 0; --i) {
         r = (r << 1) | ((a >> i) & 1);
