@@ -86,16 +86,20 @@ __device__ __forceinline__ u256 u256_add(u256 a, const u256& b) {
 }
 
 // floor(sqrt(x)).  Below 2^104 the root is under 2^52: a double square root
-// lands within a few units of it, and exact 128-bit squares step it to the
-// floor.  Otherwise digit by digit (binary restoring method).
+// lands within a unit or two of it, and exact 128-bit squares step it to the
+// floor (at most four steps each way; if that does not bracket the root, the
+// general method below decides).  Otherwise digit by digit (binary restoring
+// method).
 __device__ u256 u256_isqrt(u256 x) {
     if ((x.w[3] | x.w[2]) == 0 && (x.w[1] >> 40) == 0) {
         const u128 xx = static_cast<u128>(x.w[1]) << 64 | x.w[0];
         const double xd = static_cast<double>(x.w[1]) * 18446744073709551616.0 + static_cast<double>(x.w[0]);
         uint64_t r = static_cast<uint64_t>(sqrt(xd));
-        while (r > 0 && static_cast<u128>(r) * r > xx) --r;
-        while (static_cast<u128>(r + 1) * (r + 1) <= xx) ++r;
-        return u256{{r, 0, 0, 0}};
+        if (r > (uint64_t(1) << 53)) r = uint64_t(1) << 53;
+        for (int i = 0; i < 4 && r > 0 && static_cast<u128>(r) * r > xx; ++i) --r;
+        for (int i = 0; i < 4 && static_cast<u128>(r + 1) * (r + 1) <= xx; ++i) ++r;
+        if (static_cast<u128>(r) * r <= xx && static_cast<u128>(r + 1) * (r + 1) > xx)
+            return u256{{r, 0, 0, 0}};
     }
     u256 res{{0, 0, 0, 0}};
     u256 bit{{0, 0, 0, 0}};
