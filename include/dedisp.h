@@ -589,6 +589,8 @@ dedisp_status dedisp_rfi_apply(uint8_t* const* beams_2bit, int32_t nbeams, int32
  *   NULL.  loss: host, may be NULL (then no synchronisation).
  * triage_tiles: tiles of n_events device events from a dedispersed uint16
  *   series block and the workspace of the find_peaks call that found them.
+ * triage_score: the candidates' scores (sigmoid of the logit) only;
+ *   triage_forward gives the logits and, optionally, the scores as well.
  * triage_set_params / triage_get_params: host float32 arrays of
  *   triage_num_params() values in the order w1[32][1][3][3], b1, w2, b2,
  *   w3, b3, w4, b4 ([32][32][3][3] and [32]), wf[32], bf[1]; grads (may be
@@ -604,6 +606,8 @@ dedisp_status triage_tiles(const void* series_u16, int32_t ndm, int64_t nout, co
                            int32_t n_events, uint16_t* tiles_out, dedisp_stream stream);
 dedisp_status triage_forward(triage_model m, const uint16_t* tiles_bf16, int32_t n, float* logits,
                              float* scores, dedisp_stream stream);
+dedisp_status triage_score(triage_model m, const uint16_t* tiles_bf16, int32_t n, float* scores,
+                           dedisp_stream stream);
 dedisp_status triage_forward_backward(triage_model m, const uint16_t* tiles_bf16,
                                       const float* labels, int32_t n, float* loss,
                                       dedisp_stream stream);

@@ -139,6 +139,7 @@ def lib() -> C.CDLL:
         "triage_get_params": (i32, [vp, P(f32), P(f32), i32]),
         "triage_tiles": (i32, [vp, i32, i64, P(i32), i32, vp, vp, i32, vp, vp]),
         "triage_forward": (i32, [vp, vp, i32, vp, vp, vp]),
+        "triage_score": (i32, [vp, vp, i32, vp, vp]),
         "triage_forward_backward": (i32, [vp, vp, vp, i32, P(f32), vp]),
         "triage_train_step": (i32, [vp, vp, vp, i32, f32, P(f32), vp]),
         "triage_save": (i32, [vp, C.c_char_p]),
@@ -725,6 +726,10 @@ def triage_tiles(series, ndm: int, nout: int, widths, peaks_ws, events_dev, n_ev
 def triage_forward(m: Model, tiles, n: int, logits=None, scores=None, stream=None):
     _check(lib().triage_forward(m.handle, _ptr(tiles), int(n), _ptr(logits), _ptr(scores),
                                 _stream(stream)))
+
+
+def triage_score(m: Model, tiles, n: int, scores, stream=None):
+    _check(lib().triage_score(m.handle, _ptr(tiles), int(n), _ptr(scores), _stream(stream)))
 
 
 def triage_forward_backward(m: Model, tiles, labels, n: int, stream=None) -> float:

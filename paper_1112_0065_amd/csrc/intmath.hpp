@@ -1,11 +1,28 @@
-// Exact wide-integer helpers of the sigma-cut (device code): 128/256-bit
-// sums, products, shifts, integer square root and division, and the cut
-// level B_thr of a series from its exact sums.
+// Exact wide-integer helpers of the sigma-cut: 128/256-bit sums, products,
+// shifts, integer square root and division, and the cut level B_thr of a
+// series from its exact sums.  Plain integer code for the device and the host
+// alike, so the CPU test suite checks every branch with g++.
 #pragma once
 
-#include <hip/hip_runtime.h>
-
+#include <cmath>
 #include <cstdint>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define IM_HD __host__ __device__ __forceinline__
+#define IM_HD_NOINLINE __host__ __device__
+#else
+#define IM_HD inline
+#define IM_HD_NOINLINE inline
+#endif
+
+// Added to the double estimate of the integer square root before it is
+// stepped to the exact floor; nonzero only in a host test build, to drive
+// the estimate out of reach of the bounded steps (the general method then
+// decides).
+#ifndef INTMATH_ISQRT_NUDGE
+#define INTMATH_ISQRT_NUDGE 0
+#endif
 
 namespace {
 
@@ -15,19 +32,19 @@ struct u256 {
     uint64_t w[4];
 };
 
-__device__ __forceinline__ u256 u256_from(u128 x) {
+IM_HD u256 u256_from(u128 x) {
     return u256{{static_cast<uint64_t>(x), static_cast<uint64_t>(x >> 64), 0, 0}};
 }
 
 // a * b for a < 2^128, b < 2^64.
-__device__ __forceinline__ u256 u256_mul_u64(u128 a, uint64_t b) {
+IM_HD u256 u256_mul_u64(u128 a, uint64_t b) {
     const uint64_t a0 = static_cast<uint64_t>(a), a1 = static_cast<uint64_t>(a >> 64);
     const u128 p0 = static_cast<u128>(a0) * b;
     const u128 p1 = static_cast<u128>(a1) * b + (p0 >> 64);
     return u256{{static_cast<uint64_t>(p0), static_cast<uint64_t>(p1), static_cast<uint64_t>(p1 >> 64), 0}};
 }
 
-__device__ __forceinline__ u256 u256_shr(u256 a, int s) {
+IM_HD u256 u256_shr(u256 a, int s) {
     u256 r{{0, 0, 0, 0}};
     const int q = s >> 6, b = s & 63;
     for (int i = 0; i < 4; ++i) {
@@ -41,7 +58,7 @@ __device__ __forceinline__ u256 u256_shr(u256 a, int s) {
     return r;
 }
 
-__device__ __forceinline__ u256 u256_shl(u256 a, int s) {
+IM_HD u256 u256_shl(u256 a, int s) {
     u256 r{{0, 0, 0, 0}};
     const int q = s >> 6, b = s & 63;
     for (int i = 3; i >= 0; --i) {
@@ -55,13 +72,13 @@ __device__ __forceinline__ u256 u256_shl(u256 a, int s) {
     return r;
 }
 
-__device__ __forceinline__ bool u256_ge(const u256& a, const u256& b) {
+IM_HD bool u256_ge(const u256& a, const u256& b) {
     for (int i = 3; i >= 0; --i)
         if (a.w[i] != b.w[i]) return a.w[i] > b.w[i];
     return true;
 }
 
-__device__ __forceinline__ u256 u256_sub(u256 a, const u256& b) {
+IM_HD u256 u256_sub(u256 a, const u256& b) {
     uint64_t borrow = 0;
     for (int i = 0; i < 4; ++i) {
         const uint64_t x = a.w[i], y = b.w[i];
@@ -72,7 +89,7 @@ __device__ __forceinline__ u256 u256_sub(u256 a, const u256& b) {
     return a;
 }
 
-__device__ __forceinline__ u256 u256_add(u256 a, const u256& b) {
+IM_HD u256 u256_add(u256 a, const u256& b) {
     uint64_t carry = 0;
     for (int i = 0; i < 4; ++i) {
         const uint64_t s = a.w[i] + b.w[i];
@@ -90,11 +107,11 @@ __device__ __forceinline__ u256 u256_add(u256 a, const u256& b) {
 // floor (at most four steps each way; if that does not bracket the root, the
 // general method below decides).  Otherwise digit by digit (binary restoring
 // method).
-__device__ u256 u256_isqrt(u256 x) {
+IM_HD_NOINLINE u256 u256_isqrt(u256 x) {
     if ((x.w[3] | x.w[2]) == 0 && (x.w[1] >> 40) == 0) {
         const u128 xx = static_cast<u128>(x.w[1]) << 64 | x.w[0];
         const double xd = static_cast<double>(x.w[1]) * 18446744073709551616.0 + static_cast<double>(x.w[0]);
-        uint64_t r = static_cast<uint64_t>(sqrt(xd));
+        uint64_t r = static_cast<uint64_t>(sqrt(xd)) + INTMATH_ISQRT_NUDGE;
         if (r > (uint64_t(1) << 53)) r = uint64_t(1) << 53;
         for (int i = 0; i < 4 && r > 0 && static_cast<u128>(r) * r > xx; ++i) --r;
         for (int i = 0; i < 4 && static_cast<u128>(r + 1) * (r + 1) <= xx; ++i) ++r;
@@ -125,7 +142,7 @@ __device__ u256 u256_isqrt(u256 x) {
 
 // floor(a / b), a < 2^128, b >= 1: one 64-bit division when a fits 64 bits,
 // else shift-subtract.
-__device__ u128 u128_div_u64(u128 a, uint64_t b) {
+IM_HD_NOINLINE u128 u128_div_u64(u128 a, uint64_t b) {
     if ((a >> 64) == 0) return static_cast<uint64_t>(a) / b;
     u128 q = 0, r = 0;
     for (int i = 127; i >= 0; --i) {
@@ -139,7 +156,7 @@ __device__ u128 u128_div_u64(u128 a, uint64_t b) {
 }
 
 // Round-to-nearest-even conversion of an unsigned 128-bit integer.
-__device__ double u128_to_double(u128 x) {
+IM_HD_NOINLINE double u128_to_double(u128 x) {
     if ((x >> 64) == 0) return static_cast<double>(static_cast<uint64_t>(x));
     const uint64_t hi = static_cast<uint64_t>(x >> 64);
     const int lz = __builtin_clzll(hi);
@@ -157,7 +174,7 @@ __device__ double u128_to_double(u128 x) {
 //   B_thr = ceil((S1 + isqrt(floor(k^2 D)) + 1) / n).
 // Returns -1 when D == 0 (nothing exceeds) and INT64_MAX when no value below
 // 2^62 can; *d_out (may be NULL) receives D.
-__device__ int64_t cut_level(uint64_t n, uint64_t s1, u128 s2, uint32_t kmant, int kexp2,
+IM_HD_NOINLINE int64_t cut_level(uint64_t n, uint64_t s1, u128 s2, uint32_t kmant, int kexp2,
                              u128* d_out) {
     const u128 d = static_cast<u128>(n) * s2 - static_cast<u128>(s1) * s1;
     if (d_out) *d_out = d;

@@ -326,30 +326,8 @@ __device__ __forceinline__ void width_sums(const uint32_t* pl, int npos, int w, 
     *mx_out = mx;
 }
 
-// The common case -- a full segment of kPerThread * 256 positions and small
-// values -- with every loop unrolled: each thread keeps its 32 running-sum
-// bases in registers and reads one running sum per (width, position).
+// Positions per thread in the fast path of a full segment.
 constexpr int kPerThread = 32;
-
-__device__ __forceinline__ void width_sums_full(const uint32_t* pl, const uint32_t (&p0)[kPerThread],
-                                                int w, uint64_t* s1_out, u128* s2_out,
-                                                uint32_t* mx_out) {
-    uint32_t s1 = 0, mx = 0;   // 32 terms below 2^26: no overflow
-    uint64_t s2 = 0;
-    const uint32_t* q = pl + 1 + w + threadIdx.x;
-#pragma unroll
-    for (int j = 0; j < kPerThread; ++j) {
-        const uint32_t b = q[j * kThreads] - p0[j];
-        s1 += b;
-        s2 += static_cast<uint64_t>(b) * b;
-        mx = max(mx, b);
-    }
-    *s1_out = wave_sum_u64(s1);
-    *s2_out = wave_sum_u64(s2);
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) mx = max(mx, static_cast<uint32_t>(__shfl_xor(mx, o, 64)));
-    *mx_out = mx;
-}
 
 // Fast path of a full segment with small values and NW (compile-time)
 // widths: positions outer, widths inner, every partial sum in registers, then
@@ -467,11 +445,16 @@ __global__ __launch_bounds__(kThreads) void boxcar_stats_kernel(const T* __restr
     load_prefix(in + static_cast<int64_t>(d) * nout, nout, s0 - 1, n, pl, wave_tot, &vmax);
     const int npos = static_cast<int>(min<int64_t>(L, nbx - s0));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const bool small = static_cast<uint64_t>(vmax) * static_cast<uint64_t>(w_max) < (uint64_t(1) << 26);
-    // full fast path: a whole segment, squares summable in 64 bits, and every
-    // sum of L consecutive samples below 2^32 (for the telescoped S1)
-    const bool full = small && npos == kPerThread * kThreads && vmax < (1u << 19) &&
-                      L == kPerThread * kThreads;
+    const uint64_t bmax = static_cast<uint64_t>(vmax) * static_cast<uint64_t>(w_max);
+    // every boxcar below 2^26: a wave's 64-bit square sum (at most 64 x 32
+    // squares below 2^52) cannot overflow
+    const bool small = bmax < (uint64_t(1) << 26);
+    // full fast path: a whole segment whose square sum, over all its
+    // kPerThread * 256 = 2^13 positions, stays below 2^13 * 2^50 = 2^63 (every
+    // boxcar below 2^25), and every sum of L consecutive samples below 2^32
+    // (for the telescoped S1)
+    const bool full = bmax < (uint64_t(1) << 25) && npos == kPerThread * kThreads &&
+                      vmax < (1u << 19) && L == kPerThread * kThreads;
     constexpr int NWS = NW > 0 ? NW : 1;
     if (NW > 0 && full) {
         __shared__ uint64_t f1[NWS];

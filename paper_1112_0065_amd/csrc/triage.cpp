@@ -198,6 +198,12 @@ extern "C" dedisp_status triage_forward(triage_model m, const uint16_t* tiles_bf
     return DEDISP_OK;
 }
 
+extern "C" dedisp_status triage_score(triage_model m, const uint16_t* tiles_bf16, int32_t n,
+                                      float* scores, dedisp_stream stream) {
+    if (!scores) return fail(DEDISP_ERR_INVALID_ARG, "NULL scores");
+    return triage_forward(m, tiles_bf16, n, nullptr, scores, stream);
+}
+
 extern "C" dedisp_status triage_forward_backward(triage_model m, const uint16_t* tiles_bf16,
                                                  const float* labels, int32_t n, float* loss,
                                                  dedisp_stream stream) {

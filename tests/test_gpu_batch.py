@@ -146,3 +146,62 @@ def test_autotune_small_config(tmp_path):
     # batch reading the same cache uses the tuned shape
     b = L.dedisp_batch_create([p2], WIDTHS, 5.0, tune_cache_path=cache)
     assert L.dedisp_batch_info(b)[0] == best
+
+
+def test_batch_at_multibeam_survey_shape():
+    """The shape the benchmark times: 13 beams of 1024 channels and 1200
+    trials, lengths 2^17 + 2^15 b and DM ranges to 500 + 125 ((5b) mod 13)
+    (beam b reads a prefix of one seeded pool), widths 1..512, S/N > 6.  The
+    batch's outputs and events are byte-equal to the single-beam path for
+    every beam; sampled rows of every beam, and their events, equal the
+    oracle's."""
+    from paper_1112_0065_amd import _lib as L
+    from oracle.peaks import series_events
+    torch = torch_dev()
+    shapes = synth.multibeam_shapes()
+    nmax = max(n for n, _ in shapes)
+    pool = synth.fast_chunk(300, nmax, npulses=20)
+    widths = [1 << i for i in range(10)]
+    plans, ins, outs, evs, ns = [], [], [], [], []
+    for b, (n, dm_max) in enumerate(shapes):
+        p = L.dedisp_plan_create(1024, synth.F_TOP, synth.DF_SURVEY, synth.TSAMP,
+                                 synth.dm_list_expm1(1200, dm_max))
+        plans.append(p)
+        ins.append(to_dev(pool[: n * 256]))
+        outs.append(torch.empty((1200, n - p.max_delay), dtype=torch.int16, device="cuda"))
+        evs.append(torch.empty((1 << 20) * 40, dtype=torch.uint8, device="cuda"))
+        ns.append(n)
+    batch = L.dedisp_batch_create(plans, widths, 6.0, out_u16=True)
+    log("multibeam batch", L.dedisp_batch_info(batch)[:2])
+    counts = L.dedisp_batch_execute(batch, ins, ns, outs, evs, [1 << 20] * 13)
+    torch.cuda.synchronize()
+    log("multibeam events per beam", counts)
+    x_all = oracle.unpack_2bit(pool, nmax, 1024)
+    rng = np.random.default_rng(13)
+    for b, (p, n) in enumerate(zip(plans, ns)):
+        nout = n - p.max_delay
+        ws = torch.empty(L.dedisp_workspace_bytes(p, n), dtype=torch.uint8, device="cuda")
+        single = torch.empty((1200, nout), dtype=torch.int16, device="cuda")
+        L.dedisp_execute(p, ins[b], n, single, ws)
+        pws = torch.empty(L.find_peaks_workspace_bytes(1200, nout, widths), dtype=torch.uint8,
+                          device="cuda")
+        evb = torch.empty((1 << 20) * 40, dtype=torch.uint8, device="cuda")
+        ns_ev = L.find_peaks(single, 1200, nout, widths, 6.0, evb, 1 << 20, pws)
+        assert torch.equal(outs[b], single), b
+        b_ev = L.events_from_buffer(evs[b], counts[b])
+        assert ns_ev == counts[b] and b_ev.tobytes() == L.events_from_buffer(evb, ns_ev).tobytes(), b
+        del single, pws, evb, ws
+        # sampled rows against the oracle
+        rows = sorted({0, 1199, int(rng.integers(1, 1199))})
+        dly = oracle.delay_table(1024, synth.F_TOP, synth.DF_SURVEY, synth.TSAMP,
+                                 synth.dm_list_expm1(1200, shapes[b][1]))
+        ref = oracle.dedisperse(x_all[:, :n], dly[rows], nout=nout)
+        got = outs[b][rows].cpu().numpy().view(np.uint16).astype(np.int64)
+        assert (got == ref).all(), b
+        bw = oracle.boxcar(ref, widths)
+        for j, d in enumerate(rows):
+            for wi in range(len(widths)):
+                want = series_events(bw[wi, j], 6.0, wi, d)
+                mine = [e for e in b_ev if int(e["width_idx"]) == wi and int(e["dm_idx"]) == d]
+                events_equal(mine, want)
+        log("beam", b, "n", n, "events", counts[b], "rows", rows, "ok")

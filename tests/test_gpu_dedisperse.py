@@ -175,39 +175,44 @@ def test_too_few_samples_and_bad_args():
         assert e.value.status == L.ERR_INVALID_ARG
 
 
-def test_survey_config_full_size_sampled_rows():
+def test_survey_config_whole_output_and_events():
     """Survey-shaped beam at full size (2^19 samples, 1024 channels, 1200
-    trials), default tile, both output types: sampled rows against the oracle
-    (first, last, each pulse's nearest trial, random)."""
+    trials), default tile, both output types: every element of the output
+    equals the oracle's, and the whole event list of find_peaks on it (widths
+    1..512, S/N > 6) equals the oracle's events of every (width, DM) series.
+    The oracle runs on all host cores (forked workers)."""
+    import time
     torch = torch_dev()
     from paper_1112_0065_amd import _lib as L
+    from gpu_common import events_equal, oracle_all_rows
     fb = survey_case()
     p = L.dedisp_plan_create(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list)
     dly = oracle.delay_table(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list)
     assert p.max_delay == 20476
-    rng = np.random.default_rng(7)
-    rows = {0, len(fb.dm_list) - 1}
-    rows |= {int(np.argmin(np.abs(fb.dm_list - pu.dm))) for pu in fb.pulses[:6]}
-    rows |= set(rng.integers(0, len(fb.dm_list), 4).tolist())
-    rows = sorted(rows)
-    x = oracle.unpack_2bit(fb.packed, fb.nsamps, fb.nchans)
-    ref = oracle.dedisperse(x, dly[rows], nout=fb.nsamps - 20476)
+    nout = fb.nsamps - 20476
     inp = to_dev(fb.packed)
     ws = torch.empty(L.dedisp_workspace_bytes(p, fb.nsamps), dtype=torch.uint8, device="cuda")
+    host = []
     for dtype in (torch.int16, torch.int32):
-        out = torch.empty((1200, fb.nsamps - 20476), dtype=dtype, device="cuda")
+        out = torch.empty((1200, nout), dtype=dtype, device="cuda")
         log("survey full size", dtype)
         L.dedisp_execute(p, inp, fb.nsamps, out, ws)
         torch.cuda.synchronize()
-        got = as_i64(out[rows])
-        assert (got == ref).all(), dtype
-        # whole-output property: every trial's total equals the sum of the
-        # windows it reads (from per-channel running sums of the input)
-        tot = out.to(torch.int64).sum(dim=1).cpu().numpy()
-        cx = np.zeros((fb.nchans, fb.nsamps + 1), np.int64)
-        np.cumsum(x, axis=1, out=cx[:, 1:])
-        nout = fb.nsamps - 20476
-        ch = np.arange(fb.nchans)
-        want = np.array([int((cx[ch, dly[d] + nout] - cx[ch, dly[d]]).sum()) for d in range(1200)])
-        assert (tot == want).all(), dtype
+        if dtype == torch.int16:
+            pws = torch.empty(L.find_peaks_workspace_bytes(1200, nout, fb.widths),
+                              dtype=torch.uint8, device="cuda")
+            evb = torch.empty((1 << 20) * 40, dtype=torch.uint8, device="cuda")
+            n = L.find_peaks(out, 1200, nout, fb.widths, fb.snr_thresh, evb, 1 << 20, pws)
+            ev = L.events_from_buffer(evb, n)
+            host.append(out.cpu().numpy().view(np.uint16))
+            del pws, evb
+        else:
+            host.append(out.cpu().numpy())
         del out
+    x = oracle.unpack_2bit(fb.packed, fb.nsamps, fb.nchans)
+    t0 = time.time()
+    bad, ref_ev = oracle_all_rows(x, dly, nout, host, fb.widths, fb.snr_thresh)
+    log("oracle over all 1200 rows", round(time.time() - t0, 1), "s; mismatches", bad,
+        "events gpu", len(ev), "oracle", len(ref_ev))
+    assert bad == [0, 0]
+    events_equal(ev, ref_ev)

@@ -221,3 +221,44 @@ def test_find_peaks_large_values_exact():
     ev, (g1, g2, gt) = _find(series, widths, 3.0, False)
     assert (g1 == s1).all() and (g2 == s2).all() and (gt == thr).all()
     events_equal(ev, ref)
+
+
+def test_find_peaks_square_sum_near_2_64():
+    """Full 8192-position segments whose boxcars lie just below 2^26: each
+    segment's sum of squares exceeds 2^64 (8192 x (5e7)^2 = 2.0e19), so the
+    64-bit fast path must not take them; the sums stay exact."""
+    rng = np.random.default_rng(95)
+    series = rng.integers(95000, 100000, size=(2, 20000)).astype(np.int64)
+    widths = [1, 512]
+    bw = oracle.boxcar(series, widths)
+    assert int(bw.max()) < (1 << 26)
+    seg_s2 = int((bw[1, 0, :8192].astype(object) ** 2).sum())
+    assert seg_s2 >= (1 << 64)
+    ref = oracle.find_events(bw, 3.0)
+    s1, s2, thr = _ref_stats(bw, 3.0)
+    ev, (g1, g2, gt) = _find(series, widths, 3.0, False)
+    assert (g1 == s1).all() and (g2 == s2).all() and (gt == thr).all()
+    events_equal(ev, ref)
+
+
+@pytest.mark.parametrize("k", [6.0, 1.0e6])
+def test_find_peaks_wide_integer_paths(k):
+    """Series of 2^18 values uniform below 2^27 with widths up to 16: at
+    k = 1e6, k^2 D exceeds 2^104 (the digit-by-digit square root) and
+    S1 + isqrt(k^2 D) + 1 exceeds 2^64 (the bit-serial division); at k = 6
+    both stay on their fast paths.  Thresholds equal the oracle's."""
+    rng = np.random.default_rng(26)
+    series = rng.integers(0, 1 << 27, size=(2, 1 << 18)).astype(np.int64)
+    widths = [1, 16]
+    bw = oracle.boxcar(series, widths)
+    assert int(bw.max()) < (1 << 31)
+    s1, s2, thr = _ref_stats(bw, k)
+    if k > 1000:
+        n = bw.shape[2]
+        d = n * int(s2[1, 0]) - int(s1[1, 0]) ** 2
+        assert int(k * k) * d >= (1 << 104)
+        assert int(s1[1, 0]) + int(k * np.sqrt(float(d))) >= (1 << 64)
+    ref = oracle.find_events(bw, k)
+    ev, (g1, g2, gt) = _find(series, widths, k, False)
+    assert (g1 == s1).all() and (g2 == s2).all() and (gt == thr).all()
+    events_equal(ev, ref)

@@ -87,7 +87,9 @@ def test_stream_matches_oracle_windows():
 
 
 def test_alone_equals_in_mix():
-    """A beam's chunk gives identical events alone and among 13 beams."""
+    """Every beam's chunks give identical events alone and among 13 beams,
+    and the mix really ran as continuous batches (several beams' chunks in
+    one launch)."""
     from paper_1112_0065_amd import _lib as L
     torch_dev()
     fbs = [_stream(800 + b, 2, 60.0 + 10 * b) for b in range(13)]
@@ -102,7 +104,9 @@ def test_alone_equals_in_mix():
     st = L.dedisp_serve_stats(mix)
     log("mix stats", st)
     mix.close()
-    for b in (0, 6, 12):
+    assert st["max_batch"] >= 2, st
+    assert st["batches"] < 26, st
+    for b in range(13):
         alone = L.dedisp_serve_create([plans[b]], C, WIDTHS, K, budget)
         for k in range(2):
             assert L.dedisp_serve_submit(alone, 0, k, _chunk(fbs[b], k), L.dedisp_now_ns())

@@ -77,6 +77,25 @@ def test_forward_backward_match_oracle():
         assert num / den <= 2e-2, k
 
 
+def test_score_is_sigmoid_of_forward_logit():
+    from paper_1112_0065_amd import _lib as L
+    torch = torch_dev()
+    p = _params(2)
+    bits, vals = _tiles(9, 5)
+    m = L.triage_create(None, 0)
+    L.triage_set_params(m, flat(p))
+    t = _dev_tiles(bits)
+    logits = torch.empty(5, dtype=torch.float32, device="cuda")
+    scores = torch.empty(5, dtype=torch.float32, device="cuda")
+    L.triage_forward(m, t, 5, logits=logits)
+    L.triage_score(m, t, 5, scores)
+    torch.cuda.synchronize()
+    ref_logits, _ = cnn.forward(p, vals, bf16=True)
+    lg = logits.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(lg - ref_logits) <= 1e-2 * (1 + np.abs(ref_logits)))
+    assert np.allclose(scores.cpu().numpy(), 1.0 / (1.0 + np.exp(-lg)), rtol=1e-6, atol=1e-7)
+
+
 def test_adam_step_matches_oracle():
     from paper_1112_0065_amd import _lib as L
     torch = torch_dev()
@@ -93,6 +112,40 @@ def test_adam_step_matches_oracle():
     vv = {k: np.zeros_like(np.asarray(v, np.float64)) for k, v in p.items()}
     want = cnn.adam_step(p, unflat(g), mm, vv, 1, lr=1e-3)
     assert np.allclose(new, flat(want), rtol=1e-5, atol=1e-7)
+
+
+def test_adam_chain_of_steps_matches_oracle():
+    """Six consecutive training steps on batches whose labels flip and whose
+    tiles change, so the gradients change sign and size from step to step:
+    after every step the GPU's parameters equal a chain of oracle Adam steps
+    (t = 1..6, the moments carried over) fed the GPU's own gradients.  Step
+    counts, both decay rates and the bias corrections all enter from the
+    second step on."""
+    from paper_1112_0065_amd import _lib as L
+    torch = torch_dev()
+    p = _params(4)
+    m = L.triage_create(None, 0)
+    L.triage_set_params(m, flat(p))
+    mm = {k: np.zeros_like(np.asarray(v, np.float64)) for k, v in p.items()}
+    vv = {k: np.zeros_like(np.asarray(v, np.float64)) for k, v in p.items()}
+    ref = {k: np.asarray(v, np.float32) for k, v in p.items()}
+    lr = 2e-3
+    prev_g = None
+    for t in range(1, 7):
+        bits, _ = _tiles(40 + t, 8)
+        labels = np.array([1, 0] * 4 if t % 2 else [0, 1] * 4, np.float64)
+        lab = torch.tensor(labels, dtype=torch.float32, device="cuda")
+        L.triage_train_step(m, _dev_tiles(bits), lab, 8, lr=lr)
+        new, g = L.triage_get_params(m)
+        ref = cnn.adam_step(ref, unflat(g), mm, vv, t, lr=lr)
+        want = flat(ref)
+        err = np.abs(new - want).max()
+        log("adam step", t, "max |gpu - oracle|", err)
+        assert np.allclose(new, want, rtol=1e-5, atol=1e-7), t
+        if prev_g is not None:
+            assert (np.sign(g) != np.sign(prev_g)).mean() > 0.1   # the gradients really change
+        prev_g = g
+        ref = {k: np.asarray(v, np.float32) for k, v in unflat(new).items()}
 
 
 def test_training_reproducible_and_resumable(tmp_path):

@@ -122,3 +122,36 @@ def test_tile_origin_and_values():
     n, s1, s2 = stats[0]
     assert t[0, 0] == cnn.round_bf16(np.float32((0 * n - s1) / math.sqrt(n * s2 - s1 * s1)))
     assert (t[:, 100:] == 0).all()
+
+
+def test_adam_three_steps_hand_computed():
+    """Three Adam steps on two parameters whose gradients change sign and
+    size at every step, so that the moment decays (beta1 = 0.9 on the mean,
+    beta2 = 0.999 on the square), the bias corrections 1 - beta^t and the
+    step count all change the result.  Expected values worked out by hand
+    from the update
+        m_t = b1 m_{t-1} + (1 - b1) g_t,   v_t = b2 v_{t-1} + (1 - b2) g_t^2,
+        p_t = p_{t-1} - lr (m_t / (1 - b1^t)) / (sqrt(v_t / (1 - b2^t)) + eps)
+    with lr = 0.1; e.g. for the first parameter at t = 2:
+        m_2 = 0.9 * 0.05 + 0.1 * (-2) = -0.155,
+        v_2 = 0.999 * 0.00025 + 0.001 * 4 = 0.00424975,
+        m_2 / 0.19 = -0.815789..., v_2 / 0.001999 = 2.125938...,
+        p_2 = 0.9 + 0.1 * 0.815789 / 1.458060 = 0.955950.
+    (Swapping beta1 and beta2 gives 0.950337 there; running step 2 with
+    t = 1 gives 0.997405.)"""
+    p = {"a": np.array([1.0, -0.5], np.float32)}
+    gs = [np.array([0.5, 1e-3]), np.array([-2.0, 3.0]), np.array([0.25, -0.5])]
+    want = [np.array([0.9000000020, -0.5999990000]),
+            np.array([0.9559503510, -0.6744350020]),
+            np.array([0.9911908279, -0.7206834531])]
+    want_m = [np.array([0.05, 1e-4]), np.array([-0.155, 0.30009]), np.array([-0.1145, 0.220081])]
+    want_v = [np.array([2.5e-4, 1e-9]), np.array([0.00424975, 0.009000000999]),
+              np.array([0.00430800025, 0.009241000998001])]
+    m = {"a": np.zeros(2)}
+    v = {"a": np.zeros(2)}
+    for t in range(1, 4):
+        p = cnn.adam_step(p, {"a": gs[t - 1]}, m, v, t, lr=0.1)
+        assert p["a"].dtype == np.float32
+        assert np.allclose(m["a"], want_m[t - 1], rtol=1e-12, atol=0)
+        assert np.allclose(v["a"], want_v[t - 1], rtol=1e-12, atol=0)
+        assert np.allclose(p["a"], want[t - 1], rtol=0, atol=2e-7), (t, p["a"], want[t - 1])
