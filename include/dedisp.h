@@ -361,12 +361,16 @@ typedef struct {
     int64_t n_bx;          /* boxcar start positions searched                            */
     int64_t n_events;      /* events found (may exceed the records when OVERFLOW)        */
     const dedisp_event* events;  /* host, min(n_events, 65536) records, t relative to t_abs0 */
-    const float* scores;   /* host, triage score per event, or NULL                        */
+    const float* scores;   /* host, per event: the triage score (0..1) of the candidates
+                              dedisp_candidates_nms keeps (dm_half 32, t_half_per_width
+                              128), -1 for the events it suppresses; NULL without a
+                              network (FALLBACK)                                          */
     int64_t arrival_ns, done_ns;
     int32_t flags;
     int64_t n_clusters;    /* clusters of the kept events (CLUSTERED), else 0           */
     const dedisp_cluster* clusters;  /* host, n_clusters records, t relative to t_abs0,
                                         rep/first index the chunk's events, or NULL      */
+    int64_t n_candidates;  /* events scored by the network (0 without scores)           */
 } dedisp_chunk_result;
 
 typedef struct {
@@ -527,6 +531,24 @@ dedisp_status dedisp_trigger_windows(const dedisp_cluster* clusters, int64_t n,
                                      int64_t* n_out);
 
 /* ------------------------------------------------------------------------
+ * Candidate selection for triage (host code).  Per boxcar width w, events
+ * are visited from the highest snr down (ties: lower dm_idx, then earlier
+ * t_peak, then lower index) and one is kept unless an already kept event of
+ * the same width lies within dm_half trials and t_half_per_width * w samples
+ * of it, both strictly (|d_a - d_b| < dm_half and |t_a - t_b| < t_half * w).
+ * The triage network is trained on, and the server scores, the events this
+ * keeps with dm_half = 32 and t_half_per_width = 128: one candidate per
+ * 64-trial x 256 w-sample tile.
+ * events: host, n >= 0 in any order; widths: host, nwidths values >= 1 that
+ * width_idx indexes.  keep_out: host, room for n indices; receives the kept
+ * indices in ascending order, *n_keep (host) their number.
+ * Errors: INVALID_ARG (NULL, bad sizes, width_idx outside the list).
+ * ------------------------------------------------------------------------ */
+dedisp_status dedisp_candidates_nms(const dedisp_event* events, int64_t n, const int32_t* widths,
+                                    int32_t nwidths, int32_t dm_half, int32_t t_half_per_width,
+                                    int64_t* keep_out, int64_t* n_keep);
+
+/* ------------------------------------------------------------------------
  * Multibeam coincidence RFI mask (section 2.1: interference is not localised,
  * so the beams of the multibeam receiver act as reference antennas for one
  * another; a sample where enough beams exceed a S/N threshold is flagged).
@@ -614,6 +636,37 @@ dedisp_status triage_forward_backward(triage_model m, const uint16_t* tiles_bf16
 dedisp_status triage_train_step(triage_model m, const uint16_t* tiles_bf16, const float* labels,
                                 int32_t n, float lr, float* loss, dedisp_stream stream);
 dedisp_status triage_save(triage_model m, const char* path);
+
+/* ------------------------------------------------------------------------
+ * Device description, for relating measured rates to the chip's peaks
+ * (compute units x 64 lanes x clock; HBM bandwidth).
+ *
+ * dedisp_device_info: hipGetDeviceProperties of the current device.
+ *   Synchronous, host-only output.  Errors: INVALID_ARG (NULL), HIP.
+ * dedisp_clock_probe: runs dependent 32-bit integer work on every SIMD (8
+ *   waves each) for wall_us microseconds of wall time (100..2e6) and returns
+ *   in *shader_ghz (host) the median over waves of the shader clock counter's
+ *   rate against the constant-rate wall clock: the clock the shader runs at
+ *   under full vector load.  Synchronous; allocates a small device buffer.
+ *   Errors: INVALID_ARG, UNSUPPORTED (no wall clock), HIP.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t device;
+    int32_t compute_units;
+    int32_t max_clock_khz;       /* peak shader clock */
+    int32_t memory_clock_khz;
+    int32_t memory_bus_bits;
+    int32_t l2_bytes;            /* per XCD as the runtime reports it */
+    int32_t wall_clock_khz;      /* rate of the constant wall clock */
+    int32_t reserved;
+    int64_t lds_bytes_per_cu;
+    int64_t total_memory_bytes;
+    char arch[64];               /* e.g. "gfx950:sramecc+:xnack-" */
+    char name[128];
+} dedisp_device_props;
+
+dedisp_status dedisp_device_info(dedisp_device_props* out);
+dedisp_status dedisp_clock_probe(int32_t wall_us, double* shader_ghz);
 
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* dedisp_last_error(void);

@@ -28,9 +28,10 @@ from .coincidence import zero_dm_series, rfi_mask, binomial_tail, replace_masked
 from .baseline import baseline_remove
 from .cluster import cluster_events, CLUSTER_FIELDS
 from .subband import subband_dedisperse, subband_plan, effective_delays
+from .nms import nms
 
 __all__ = [
-    "baseline_remove", "cluster_events", "CLUSTER_FIELDS",
+    "baseline_remove", "cluster_events", "CLUSTER_FIELDS", "nms",
     "subband_dedisperse", "subband_plan", "effective_delays",
     "zero_dm_series", "rfi_mask", "binomial_tail", "replace_masked",
     "K_DM", "channel_freqs", "delay_table", "max_delay", "nearest_tie_distance",

@@ -53,7 +53,7 @@ class _ChunkResult(C.Structure):
                 ("n_bx", C.c_int64), ("n_events", C.c_int64), ("events", C.c_void_p),
                 ("scores", C.POINTER(C.c_float)), ("arrival_ns", C.c_int64),
                 ("done_ns", C.c_int64), ("flags", C.c_int32), ("n_clusters", C.c_int64),
-                ("clusters", C.c_void_p)]
+                ("clusters", C.c_void_p), ("n_candidates", C.c_int64)]
 
 
 class _ServeStats(C.Structure):
@@ -61,6 +61,14 @@ class _ServeStats(C.Structure):
                 ("max_ns", C.c_int64), ("deadline_ns", C.c_int64),
                 ("deadline_misses", C.c_int64), ("batches", C.c_int64),
                 ("max_batch", C.c_int64), ("mean_batch", C.c_double), ("slots", C.c_int32)]
+
+
+class _DeviceProps(C.Structure):
+    _fields_ = [("device", C.c_int32), ("compute_units", C.c_int32), ("max_clock_khz", C.c_int32),
+                ("memory_clock_khz", C.c_int32), ("memory_bus_bits", C.c_int32),
+                ("l2_bytes", C.c_int32), ("wall_clock_khz", C.c_int32), ("reserved", C.c_int32),
+                ("lds_bytes_per_cu", C.c_int64), ("total_memory_bytes", C.c_int64),
+                ("arch", C.c_char * 64), ("name", C.c_char * 128)]
 
 
 CHUNK_GAP, CHUNK_LATE, CHUNK_FALLBACK, CHUNK_OVERFLOW, CHUNK_CLUSTERED = 1, 2, 4, 8, 16
@@ -143,6 +151,9 @@ def lib() -> C.CDLL:
         "triage_forward_backward": (i32, [vp, vp, vp, i32, P(f32), vp]),
         "triage_train_step": (i32, [vp, vp, vp, i32, f32, P(f32), vp]),
         "triage_save": (i32, [vp, C.c_char_p]),
+        "dedisp_candidates_nms": (i32, [vp, i64, P(i32), i32, i32, i32, P(i64), P(i64)]),
+        "dedisp_device_info": (i32, [P(_DeviceProps)]),
+        "dedisp_clock_probe": (i32, [i32, P(f64)]),
         "dedisp_last_error": (C.c_char_p, []),
         "dedisp_version": (C.c_char_p, []),
     }
@@ -162,6 +173,36 @@ def declared_symbols() -> list:
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", text)) -
                   {"if", "sizeof", "defined"})
+
+
+def dedisp_candidates_nms(events: np.ndarray, widths, dm_half: int = 32,
+                          t_half_per_width: int = 128) -> np.ndarray:
+    """Indices (ascending) of the events kept by per-width non-maximum
+    suppression; events: host structured array of EVENT_DTYPE."""
+    ev = np.ascontiguousarray(events, dtype=EVENT_DTYPE)
+    keep = np.empty(max(len(ev), 1), np.int64)
+    nk = C.c_int64()
+    _check(lib().dedisp_candidates_nms(ev.ctypes.data if len(ev) else None, len(ev),
+                                       _i32arr(widths), len(widths), int(dm_half),
+                                       int(t_half_per_width),
+                                       keep.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(nk)))
+    return keep[:nk.value].copy()
+
+
+def dedisp_device_info() -> dict:
+    p = _DeviceProps()
+    _check(lib().dedisp_device_info(C.byref(p)))
+    out = {k: getattr(p, k) for k, _ in _DeviceProps._fields_ if k != "reserved"}
+    out["arch"] = p.arch.decode()
+    out["name"] = p.name.decode()
+    return out
+
+
+def dedisp_clock_probe(wall_us: int = 20000) -> float:
+    """Shader clock (GHz) under full vector load, median over waves."""
+    g = C.c_double()
+    _check(lib().dedisp_clock_probe(int(wall_us), C.byref(g)))
+    return float(g.value)
 
 
 def dedisp_last_error() -> str:
@@ -647,7 +688,7 @@ def dedisp_serve_poll(server: Server, cap: int = 64, timeout_ms: int = 0):
         out.append(dict(beam=r.beam, seq=r.seq, t_abs0=r.t_abs0, n_bx=r.n_bx,
                         n_events=r.n_events, events=ev, scores=scores,
                         arrival_ns=r.arrival_ns, done_ns=r.done_ns, flags=r.flags,
-                        clusters=clusters))
+                        clusters=clusters, n_candidates=r.n_candidates))
     return out
 
 

@@ -11,6 +11,8 @@
 #include <algorithm>
 #include <cinttypes>
 #include <cstdio>
+#include <cstdlib>
+#include <unordered_map>
 #include <vector>
 
 #include "dedisp_internal.hpp"
@@ -111,6 +113,75 @@ extern "C" dedisp_status dedisp_trigger_windows(const dedisp_cluster* clusters, 
     if (*n_out > capacity)
         return fail(DEDISP_ERR_CAPACITY, "%lld windows, capacity %lld",
                     static_cast<long long>(*n_out), static_cast<long long>(capacity));
+    dd::clear_error();
+    return DEDISP_OK;
+}
+
+// Candidate selection for the triage network: per-width non-maximum
+// suppression.  Within one boxcar width w, events are visited from the
+// highest S/N down (ties: lower DM, earlier t_peak, lower index); an event
+// is kept unless a kept event of the same width lies within dm_half trials
+// and t_half_per_width * w samples of it (both strict).  Kept events are
+// bucketed on a grid of dm_half x t_half * w cells, so each test looks at
+// the 3 x 3 neighbouring cells only: O(n log n) for the sort, O(n) tests.
+extern "C" dedisp_status dedisp_candidates_nms(const dedisp_event* events, int64_t n,
+                                               const int32_t* widths, int32_t nwidths,
+                                               int32_t dm_half, int32_t t_half_per_width,
+                                               int64_t* keep_out, int64_t* n_keep) {
+    if (!n_keep || (n > 0 && (!events || !keep_out)) || !widths)
+        return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
+    if (n < 0 || nwidths < 1 || dm_half < 1 || t_half_per_width < 1)
+        return fail(DEDISP_ERR_INVALID_ARG, "need n >= 0, nwidths >= 1, dm_half >= 1, t_half >= 1");
+    for (int64_t i = 0; i < n; ++i)
+        if (events[i].width_idx < 0 || events[i].width_idx >= nwidths || widths[events[i].width_idx] < 1)
+            return fail(DEDISP_ERR_INVALID_ARG, "event %lld has no valid width", static_cast<long long>(i));
+    std::vector<int64_t> order(static_cast<size_t>(n));
+    for (int64_t i = 0; i < n; ++i) order[static_cast<size_t>(i)] = i;
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+        const dedisp_event& x = events[a];
+        const dedisp_event& y = events[b];
+        if (x.width_idx != y.width_idx) return x.width_idx < y.width_idx;
+        if (x.snr != y.snr) return x.snr > y.snr;
+        if (x.dm_idx != y.dm_idx) return x.dm_idx < y.dm_idx;
+        if (x.t_peak != y.t_peak) return x.t_peak < y.t_peak;
+        return a < b;
+    });
+    std::vector<int64_t> keep;
+    std::unordered_map<uint64_t, std::vector<int64_t>> grid;
+    auto floordiv = [](int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
+    auto key = [](int64_t cd, int64_t ct) {
+        return (static_cast<uint64_t>(cd) << 40) ^ static_cast<uint64_t>(ct & ((int64_t(1) << 40) - 1));
+    };
+    int32_t cur_w = -1;
+    for (int64_t i : order) {
+        const dedisp_event& e = events[i];
+        if (e.width_idx != cur_w) {
+            grid.clear();
+            cur_w = e.width_idx;
+        }
+        const int64_t tw = static_cast<int64_t>(t_half_per_width) * widths[e.width_idx];
+        const int64_t cd = floordiv(e.dm_idx, dm_half), ct = floordiv(e.t_peak, tw);
+        bool suppressed = false;
+        for (int64_t a = cd - 1; a <= cd + 1 && !suppressed; ++a)
+            for (int64_t b = ct - 1; b <= ct + 1 && !suppressed; ++b) {
+                auto it = grid.find(key(a, b));
+                if (it == grid.end()) continue;
+                for (int64_t j : it->second) {
+                    const dedisp_event& k = events[j];
+                    if (std::llabs(static_cast<long long>(k.dm_idx) - e.dm_idx) < dm_half &&
+                        std::llabs(static_cast<long long>(k.t_peak - e.t_peak)) < tw) {
+                        suppressed = true;
+                        break;
+                    }
+                }
+            }
+        if (suppressed) continue;
+        grid[key(cd, ct)].push_back(i);
+        keep.push_back(i);
+    }
+    std::sort(keep.begin(), keep.end());
+    std::copy(keep.begin(), keep.end(), keep_out);
+    *n_keep = static_cast<int64_t>(keep.size());
     dd::clear_error();
     return DEDISP_OK;
 }

@@ -53,6 +53,7 @@ struct Slot {
     void* out = nullptr;          // uint16 series
     void* pk_ws = nullptr;        // find_peaks workspace
     dedisp_event* d_events = nullptr;
+    dedisp_event* d_cand = nullptr;     // the events triage scores (after selection)
     void* cl_ws = nullptr;              // clustering workspace (when enabled)
     dedisp_cluster* d_clusters = nullptr;
     bool busy = false;
@@ -309,13 +310,34 @@ void completer(dedisp_server_s* s) {
                 }
             }
             if (e == hipSuccess && s->model) {
+                // the network scores candidates: the events per-width
+                // non-maximum suppression keeps (the selection it was trained
+                // on); suppressed events get no score (-1)
                 const dedisp_plan_s* p = s->plans[j.beam];
                 const int64_t nout = j.nsamps - p->max_delay;
-                dedisp_status tst = dd::triage_score_events(s->model, s->slots[j.slot].out,
-                                                            s->slots[j.slot].pk_ws, p->ndm, nout, s->W,
-                                                            s->slots[j.slot].d_events, m, &r.scores,
-                                                            s->done_s);
-                if (tst != DEDISP_OK) flags |= DEDISP_CHUNK_FALLBACK;
+                const Slot& sl = s->slots[j.slot];
+                std::vector<int64_t> keep(static_cast<size_t>(std::max<int64_t>(m, 1)));
+                int64_t nk = 0;
+                dedisp_status tst = dedisp_candidates_nms(r.events.data(), m, s->W.w, s->W.n, 32, 128,
+                                                          keep.data(), &nk);
+                std::vector<dedisp_event> cand(static_cast<size_t>(nk));
+                for (int64_t k = 0; k < nk; ++k) cand[static_cast<size_t>(k)] = r.events[static_cast<size_t>(keep[k])];
+                if (tst == DEDISP_OK && nk > 0) {
+                    e = hipMemcpyAsync(sl.d_cand, cand.data(), nk * sizeof(dedisp_event),
+                                       hipMemcpyHostToDevice, s->done_s);
+                    if (e != hipSuccess) tst = DEDISP_ERR_HIP;
+                }
+                std::vector<float> cs;
+                if (tst == DEDISP_OK)
+                    tst = dd::triage_score_events(s->model, sl.out, sl.pk_ws, p->ndm, nout, s->W, sl.d_cand,
+                                                  nk, &cs, s->done_s);
+                if (tst == DEDISP_OK) {
+                    r.scores.assign(static_cast<size_t>(m), -1.0f);
+                    for (int64_t k = 0; k < nk; ++k) r.scores[static_cast<size_t>(keep[k])] = cs[static_cast<size_t>(k)];
+                    r.r.n_candidates = nk;
+                } else {
+                    flags |= DEDISP_CHUNK_FALLBACK;
+                }
             } else if (!s->model) {
                 flags |= DEDISP_CHUNK_FALLBACK;
             }
@@ -361,6 +383,7 @@ void free_server(dedisp_server_s* s) {
         if (sl.out) (void)hipFree(sl.out);
         if (sl.pk_ws) (void)hipFree(sl.pk_ws);
         if (sl.d_events) (void)hipFree(sl.d_events);
+        if (sl.d_cand) (void)hipFree(sl.d_cand);
         if (sl.cl_ws) (void)hipFree(sl.cl_ws);
         if (sl.d_clusters) (void)hipFree(sl.d_clusters);
     }
@@ -414,7 +437,7 @@ extern "C" size_t dedisp_serve_slot_bytes(const dedisp_plan* plans, int32_t nbea
     const size_t b = static_cast<size_t>(nchans) * dd::repack_words(win) * sizeof(uint2);
     const size_t c = static_cast<size_t>(ndm) * (chunk_nsamps + w_max - 1) * 2;
     const size_t d = dd::peaks_layout(static_cast<int>(ndm), chunk_nsamps + w_max - 1, W).bytes;
-    const size_t e = static_cast<size_t>(1 << 16) * sizeof(dedisp_event);
+    const size_t e = 2 * static_cast<size_t>(1 << 16) * sizeof(dedisp_event);   // events, candidates
     return a + b + c + d + e;
 }
 
@@ -510,6 +533,7 @@ extern "C" dedisp_status dedisp_serve_create(const dedisp_plan* plans, int32_t n
         if (e == hipSuccess)
             e = hipMalloc(&sl.pk_ws, dd::peaks_layout(static_cast<int>(ndm_max), s->C + w_max - 1, W).bytes);
         if (e == hipSuccess) e = hipMalloc(&sl.d_events, static_cast<size_t>(s->capacity) * sizeof(dedisp_event));
+        if (e == hipSuccess) e = hipMalloc(&sl.d_cand, static_cast<size_t>(s->capacity) * sizeof(dedisp_event));
     }
     for (int i = 0; i < dedisp_server_s::kRing && e == hipSuccess; ++i) {
         e = hipHostMalloc(&s->h_beams[i], sizeof(dd::BeamArgs) * nslots, hipHostMallocDefault);

@@ -35,24 +35,11 @@ TRAIN_SEED = 10000
 
 
 def nms(events: np.ndarray, ndm: int) -> np.ndarray:
-    """Per-width non-maximum suppression: keep the highest-S/N event of every
-    64-DM x 256*w-sample window (ties to the lower (dm, t)).  Returns indices."""
-    keep = []
-    for wi in np.unique(events["width_idx"]):
-        idx = np.nonzero(events["width_idx"] == wi)[0]
-        w = WIDTHS[int(wi)]
-        order = idx[np.lexsort((events["t_peak"][idx], events["dm_idx"][idx], -events["snr"][idx]))]
-        kd = np.empty(len(order), np.int64)
-        kt = np.empty(len(order), np.int64)
-        nk = 0
-        for i in order:
-            d, t = int(events["dm_idx"][i]), int(events["t_peak"][i])
-            if nk and np.any((np.abs(kd[:nk] - d) < 32) & (np.abs(kt[:nk] - t) < 128 * w)):
-                continue
-            kd[nk], kt[nk] = d, t
-            nk += 1
-            keep.append(int(i))
-    return np.array(sorted(keep), dtype=np.int64)
+    """Candidates: per-width non-maximum suppression (the library's
+    dedisp_candidates_nms, which the streaming server runs too): keep the
+    highest-S/N event of every 64-DM x 256*w-sample window (ties to the lower
+    (dm, t)).  Returns indices."""
+    return L.dedisp_candidates_nms(events, WIDTHS, 32, 128)
 
 
 def label(events: np.ndarray, fb, sweep_trial: np.ndarray):

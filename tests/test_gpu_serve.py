@@ -157,10 +157,12 @@ def test_gap_order_budget_and_backpressure():
 
 
 def test_serve_scores_with_trained_model():
-    """With the trained network attached, every event of a chunk gets the
-    score the standalone path (dedisperse -> find_peaks -> tiles -> forward)
-    gives the same window, bit for bit, and the FALLBACK flag stays clear;
-    without a network the flag is set and the events are unchanged."""
+    """With the trained network attached, the candidates of a chunk (the
+    events per-width non-maximum suppression keeps, as the oracle selects
+    them) get the score the standalone path (dedisperse -> find_peaks ->
+    tiles -> forward) gives the same window, bit for bit, every other event
+    gets -1, and the FALLBACK flag stays clear; without a network the flag is
+    set and the events are unchanged."""
     from paper_1112_0065_amd import _lib as L
     from paper_1112_0065_amd import triage_train as T
     torch = torch_dev()
@@ -196,14 +198,23 @@ def test_serve_scores_with_trained_model():
         # the chunk's events are the window's (times relative to t_abs0)
         assert n == r["n_events"] and n > 0
         assert ev.tobytes() == r["events"].tobytes()
-        tiles = torch.empty((n, 64, 256), dtype=torch.int16, device="cuda")
-        L.triage_tiles(out, plan.ndm, nout, WIDTHS, pws, evb, n, tiles)
-        sc = torch.empty(n, dtype=torch.float32, device="cuda")
-        L.triage_forward(model, tiles, n, scores=sc)
+        keep = oracle.nms(ev, WIDTHS)
+        assert list(L.dedisp_candidates_nms(ev, WIDTHS)) == keep
+        nk = len(keep)
+        assert r["n_candidates"] == nk and 0 < nk < n
+        cand = ev[keep]
+        evd = torch.from_numpy(np.frombuffer(cand.tobytes(), np.uint8).copy()).cuda()
+        tiles = torch.empty((nk, 64, 256), dtype=torch.int16, device="cuda")
+        L.triage_tiles(out, plan.ndm, nout, WIDTHS, pws, evd, nk, tiles)
+        sc = torch.empty(nk, dtype=torch.float32, device="cuda")
+        L.triage_score(model, tiles, nk, sc)
         torch.cuda.synchronize()
-        log("chunk", k, "events", n, "scores", r["scores"][:4])
+        log("chunk", k, "events", n, "candidates", nk, "scores", r["scores"][keep][:4])
         assert r["scores"] is not None and len(r["scores"]) == n
-        assert (sc.cpu().numpy() == r["scores"]).all()
+        assert (sc.cpu().numpy() == r["scores"][keep]).all()
+        rest = np.ones(n, bool)
+        rest[keep] = False
+        assert (r["scores"][rest] == -1.0).all()
 
 
 def test_serve_clusters_each_chunk():

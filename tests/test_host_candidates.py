@@ -97,3 +97,34 @@ def test_trigger_windows_cover_exactly_the_selected_samples():
         assert x["n_clusters"] == len(inside)
         top = max(rows[k]["snr"] for k in inside)
         assert x["snr"] == top and x["cluster"] == min(k for k in inside if rows[k]["snr"] == top)
+
+
+def test_candidate_nms_equals_oracle():
+    """The library's per-width non-maximum suppression keeps exactly the
+    oracle's candidates, on seeded event lists with many S/N ties, events on
+    the window boundaries, and several widths (host code, no GPU)."""
+    import oracle
+    from paper_1112_0065_amd import _lib as L
+    widths = [1, 2, 4, 8, 16]
+    for seed in range(8):
+        rng = np.random.default_rng(seed)
+        n = int(rng.integers(0, 2500))
+        ev = np.zeros(n, dtype=L.EVENT_DTYPE)
+        ev["width_idx"] = rng.integers(0, len(widths), n)
+        ev["dm_idx"] = rng.integers(0, 400, n)
+        ev["t_peak"] = rng.integers(0, 200000, n)
+        # boundary cases: pairs exactly 32 trials or 128 w samples apart
+        k = n // 10
+        if k:
+            ev["dm_idx"][:k] = 100 + 32 * rng.integers(0, 3, k)
+            ev["t_peak"][:k] = 5000 + 128 * np.array(widths)[ev["width_idx"][:k]] * rng.integers(0, 3, k)
+        ev["t_start"] = ev["t_peak"] - 1
+        ev["t_end"] = ev["t_peak"] + 1
+        ev["snr"] = np.round(rng.uniform(6, 12, n), 1).astype(np.float32)
+        got = L.dedisp_candidates_nms(ev, widths)
+        want = oracle.nms(ev, widths)
+        assert list(got) == want, seed
+    with pytest.raises(L.DedispError):
+        bad = np.zeros(1, dtype=L.EVENT_DTYPE)
+        bad["width_idx"] = 7
+        L.dedisp_candidates_nms(bad, widths)
