@@ -307,7 +307,7 @@ def main():
                                "widths 1..512, S/N>6",
                    "nchans": fb.nchans, "nsamps": fb.nsamps, "ndm": ndm, "nout": nout,
                    "max_delay": plan.max_delay, "widths": fb.widths, "parallelism": "1 GPU",
-                   "input_sha256": fb.sha256(), "tile": r["tile"]},
+                   "input_sha256": fb.sha256, "tile": r["tile"]},
         "autotune": r["tuned"],
         "events_per_step": n_events,
         "stages_ms": {"repack": float(np.mean(r["t_rep"])), "dedisperse": ded_ms,
@@ -409,7 +409,7 @@ def bench_small(args):
            "ms_per_step_median": pct(r["per_step_s"], 50) * 1e3,
            "ms_per_step_p95": pct(r["per_step_s"], 95) * 1e3,
            "events_per_step": r["n_events"], "tile": r["tile"], "autotune": r["tuned"],
-           "input_sha256": fb.sha256()}
+           "input_sha256": fb.sha256}
     if not args.no_cpu_baseline:
         import oracle
         from oracle import timing
