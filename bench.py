@@ -54,6 +54,7 @@ HBM_PEAK = 8e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dedisperse_survey_traffic.json")
 KERNEL_SOURCES = ["dedisperse.hip", "bitslice.hpp", "csa_tree.inc", "dedisp_internal.hpp"]
 CHUNK = 1 << 17            # streaming chunk: 8.388608 s at 64 us
+T_START = time.perf_counter()
 
 
 def log(*a):
@@ -223,6 +224,10 @@ def main():
                     help="arrival rate as a multiple of real time")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--time-budget", type=float, default=540.0,
+                    help="wall seconds (from the start of the process) the extra legs may use: a "
+                         "leg that would not end within it is skipped and recorded as skipped; "
+                         "0 = no limit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: every beam and DM trial of this workload fits one "
@@ -318,45 +323,83 @@ def main():
         "device": {**dev, "shader_clock_ghz_under_load": clock_ghz},
         "host": host_info(),
     }
+    legs = {}
+    rec["legs_s"] = legs
+
+    def leg(name, need_s, fn):
+        """Run one extra leg, timing it, unless it would overrun the budget."""
+        el = time.perf_counter() - T_START
+        if args.time_budget and el + need_s > args.time_budget:
+            log(f"skipping {name}: {el:.0f} s elapsed, about {need_s:.0f} s more needed, "
+                f"budget {args.time_budget:.0f} s")
+            legs[name] = {"skipped": True, "elapsed_s": round(el, 1), "needed_s": need_s}
+            return None
+        log(f"{name} ...")
+        t0 = time.perf_counter()
+        res = fn()
+        legs[name] = round(time.perf_counter() - t0, 1)
+        return res
+
+    legs["survey_beam"] = round(time.perf_counter() - T_START, 1)
+    # extra legs in order of priority: the 13-beam batch and streaming first
+    # (the metric's other two parts), then the small case and the next rows
     inp, ws, out, pws, evb = r["buffers"]
-    if not args.no_next:
-        rec.update(bench_next_single(args, fb, plan, out, inp, evb, n_events, ndm, nout,
-                                     rec["stages_ms"]["repack"] + ded_ms))
+    keep_ev = L.events_from_buffer(evb, n_events)
+    direct_ms = rec["stages_ms"]["repack"] + ded_ms
     del r, out, ws, pws, evb, inp
     torch.cuda.empty_cache()
-    if not args.no_small:
-        log("small 256-channel case ...")
-        rec["small_case"] = bench_small(args)
     if not args.no_multibeam:
-        log("13-beam batch ...")
-        rec["multibeam"] = bench_multibeam(args, cpu)
-        rec["rtf_13beam"] = rec["multibeam"]["rtf_batch"]
-    if not args.no_next:
-        log("13-beam coincidence mask ...")
-        rec["rfi_mask"] = bench_rfi_mask(args)
+        rec["multibeam"] = leg("13-beam batch", 40, lambda: bench_multibeam(args, cpu))
+        if rec["multibeam"]:
+            rec["rtf_13beam"] = rec["multibeam"]["rtf_batch"]
     if not args.no_serve:
-        payloads = serve_payloads()
-        log(f"13-beam streaming at the real-time rate ({args.serve_chunks} chunks per beam) ...")
-        rec["serve"] = bench_serve(args, payloads)
-        log("13-beam streaming with 3 chunk slots (forced queueing) ...")
-        rec["serve_queueing"] = bench_serve_queueing(args, payloads)
-        log("13-beam streaming, unpaced ...")
-        rec["serve_unpaced"] = bench_serve_unpaced(args, payloads)
-        rec["p99_chunk_latency_s"] = rec["serve"]["p99_s"]
-        if not args.no_cpu_baseline:
-            log("CPU oracle per streaming chunk ...")
-            rec["serve"]["cpu_oracle_per_chunk"] = cpu_chunk_time(payloads[0])
+        payloads = leg("streaming payloads", 30, serve_payloads)
+        if payloads:
+            paced_s = (args.serve_chunks + 2) * CHUNK * synth.TSAMP / args.serve_speed + 15
+            rec["serve"] = leg(f"13-beam streaming at the real-time rate ({args.serve_chunks} "
+                               "chunks per beam)", paced_s, lambda: bench_serve(args, payloads))
+            rec["serve_queueing"] = leg("13-beam streaming with 3 chunk slots (forced queueing)",
+                                        15, lambda: bench_serve_queueing(args, payloads))
+            rec["serve_unpaced"] = leg("13-beam streaming, unpaced", 20,
+                                       lambda: bench_serve_unpaced(args, payloads))
+            if rec["serve"]:
+                rec["p99_chunk_latency_s"] = rec["serve"]["p99_s"]
+                if not args.no_cpu_baseline:
+                    cc = leg("CPU oracle per streaming chunk", 25,
+                             lambda: cpu_chunk_time(payloads[0]))
+                    if cc:
+                        rec["serve"]["cpu_oracle_per_chunk"] = cc
+            del payloads
+    if not args.no_small:
+        rec["small_case"] = leg("small 256-channel case", 20, lambda: bench_small(args))
+    if not args.no_next:
+        nx = leg("survey next rows", 40, lambda: bench_next_single(args, fb, keep_ev, direct_ms))
+        if nx:
+            rec.update(nx)
+        rec["rfi_mask"] = leg("13-beam coincidence mask", 15, lambda: bench_rfi_mask(args))
+    legs["total"] = round(time.perf_counter() - T_START, 1)
     print(json.dumps(rec), flush=True)
 
 
-def bench_next_single(args, fb, plan, out, inp, evb, n_events, ndm, nout, direct_ms):
+def bench_next_single(args, fb, ev, direct_ms):
     """Next-row legs on the survey beam: baseline removal, clustering,
-    subband dedispersion."""
+    subband dedispersion.  `ev`: the beam's events (host records) from the
+    timed steps; the series is dedispersed again here."""
     import numpy as np
     import torch
 
     from paper_1112_0065_amd import _lib as L
 
+    ndm = len(fb.dm_list)
+    plan = L.dedisp_plan_create(fb.nchans, fb.f_top, fb.df, fb.tsamp, fb.dm_list)
+    nout = fb.nsamps - plan.max_delay
+    inp = torch.from_numpy(fb.packed).to("cuda")
+    ws = torch.empty(L.dedisp_workspace_bytes(plan, fb.nsamps), dtype=torch.uint8, device="cuda")
+    out = torch.empty((ndm, nout), dtype=torch.int16, device="cuda")
+    L.dedisp_execute(plan, inp, fb.nsamps, out, ws)
+    del ws
+    n_events = len(ev)
+    evb = torch.from_numpy(np.frombuffer(ev.tobytes(), np.uint8).copy()).to("cuda")
     res = {}
     # baseline removal (running mean, radius 2048) of the survey series: one
     # read and one write of the uint16 rows
@@ -385,10 +428,9 @@ def bench_next_single(args, fb, plan, out, inp, evb, n_events, ndm, nout, direct
         res["baseline"]["cpu_oracle"] = {
             "value": 16 * (nout - 2 * R) / t_c, "unit": "output samples/s", "cores": 1,
             "kind": "oracle", "sample": f"16 of {ndm} survey series ({t_c:.2f} s)"}
-    del flat
+    del flat, out
     res["cluster"] = bench_cluster(evb, n_events, ndm, fb.widths, not args.no_cpu_baseline)
-    res["subband"] = bench_subband(fb, plan, inp, evb, n_events, direct_ms,
-                                   not args.no_cpu_baseline)
+    res["subband"] = bench_subband(fb, plan, inp, ev, direct_ms, not args.no_cpu_baseline)
     return res
 
 
@@ -724,7 +766,7 @@ def bench_serve_unpaced(args, payloads):
             "p50_s": st["p50_ns"] * 1e-9, "p99_s": st["p99_ns"] * 1e-9}
 
 
-def bench_subband(fb, plan, inp, evb, n_events, direct_ms, cpu=False):
+def bench_subband(fb, plan, inp, ev_direct, direct_ms, cpu=False):
     """Subband dedispersion of the survey beam in place of the direct sum:
     time per beam (repack + both stages, HIP events on the stream; direct_ms
     is repack + direct dedispersion of the same beam), and what
@@ -736,7 +778,6 @@ def bench_subband(fb, plan, inp, evb, n_events, direct_ms, cpu=False):
     from paper_1112_0065_amd import _lib as L
 
     ndm = len(fb.dm_list)
-    ev_direct = L.events_from_buffer(evb, n_events)
 
     def best_snr(ev):
         out = []
