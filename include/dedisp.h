@@ -253,6 +253,25 @@ dedisp_status find_peaks(const void* in, dedisp_out_type in_type, int32_t ndm,
                          float snr_thresh, dedisp_event* events, int64_t capacity,
                          int64_t* n_events, void* workspace, dedisp_stream stream);
 
+/* ------------------------------------------------------------------------
+ * find_peaks without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and errors as find_peaks,
+ * minus `workspace`: the workspace is a static device array of 32 MiB, one
+ * per GPU the library runs on, held until the process ends (its address is
+ * looked up on the first call on each device).  Inputs needing more than
+ * 32 MiB (find_peaks_workspace_bytes) fail with UNSUPPORTED; the survey
+ * shape -- 1200 series of 503 812 samples, widths 1..512 -- needs 29.5 MiB.
+ * Calls on one GPU share its array: calls that overlap in time on one GPU
+ * (from several threads or streams) race and must be serialised by the
+ * caller; sequential calls need no clearing (each call initialises what it
+ * reads).  Synchronises `stream`.
+ * ------------------------------------------------------------------------ */
+dedisp_status find_peaks_noalloc(const void* in, dedisp_out_type in_type, int32_t ndm,
+                                 int64_t nout, const int32_t* widths, int32_t nwidths,
+                                 float snr_thresh, dedisp_event* events, int64_t capacity,
+                                 int64_t* n_events, dedisp_stream stream);
+
 /* Per-series statistics of the last find_peaks call that used `workspace`
  * with the same (ndm, nout, widths).  Host outputs of nwidths*ndm entries,
  * [w][d] order, any may be NULL: s1 = S1; s2_lo/s2_hi = low/high 64 bits of

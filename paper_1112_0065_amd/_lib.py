@@ -106,6 +106,7 @@ def lib() -> C.CDLL:
         "boxcar_filter": (i32, [vp, i32, i32, i64, P(i32), i32, i32, i32, vp, vp]),
         "find_peaks_workspace_bytes": (sz, [i32, i64, P(i32), i32]),
         "find_peaks": (i32, [vp, i32, i32, i64, P(i32), i32, f32, vp, i64, P(i64), vp, vp]),
+        "find_peaks_noalloc": (i32, [vp, i32, i32, i64, P(i32), i32, f32, vp, i64, P(i64), vp]),
         "find_peaks_read_stats": (i32, [vp, i32, i64, P(i32), i32, P(i64), P(C.c_uint64),
                                         P(C.c_uint64), P(i64), vp]),
         "dedisp_batch_create": (i32, [P(vp), i32, P(i32), i32, f32, i32, C.c_char_p, P(vp)]),
@@ -373,6 +374,20 @@ def find_peaks(series, ndm: int, nout: int, widths, snr_thresh: float, events, c
     st = lib().find_peaks(_ptr(series), _out_type(series), int(ndm), int(nout),
                           _i32arr(widths), len(widths), float(snr_thresh), _ptr(events),
                           int(capacity), C.byref(n), _ptr(workspace), _stream(stream))
+    if st == ERR_CAPACITY:
+        raise DedispError(st, dedisp_last_error() + f" (n_events={n.value})")
+    _check(st)
+    return int(n.value)
+
+
+def find_peaks_noalloc(series, ndm: int, nout: int, widths, snr_thresh: float, events,
+                       capacity: int, stream=None) -> int:
+    """find_peaks with the library's static per-GPU scratch as workspace (no
+    allocation; at most 32 MiB of workspace)."""
+    n = C.c_int64()
+    st = lib().find_peaks_noalloc(_ptr(series), _out_type(series), int(ndm), int(nout),
+                                  _i32arr(widths), len(widths), float(snr_thresh), _ptr(events),
+                                  int(capacity), C.byref(n), _stream(stream))
     if st == ERR_CAPACITY:
         raise DedispError(st, dedisp_last_error() + f" (n_events={n.value})")
     _check(st)

@@ -3,6 +3,7 @@
 // dedisp_status with a message for dedisp_last_error().
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "dedisp_internal.hpp"
 #include "search_internal.hpp"
@@ -242,10 +243,14 @@ extern "C" size_t find_peaks_workspace_bytes(int32_t ndm, int64_t nout, const in
     return dd::peaks_layout(ndm, nout, W).bytes;
 }
 
-extern "C" dedisp_status find_peaks(const void* in, dedisp_out_type in_type, int32_t ndm,
-                                    int64_t nout, const int32_t* widths, int32_t nwidths,
-                                    float snr_thresh, dedisp_event* events, int64_t capacity,
-                                    int64_t* n_events, void* workspace, dedisp_stream stream) {
+namespace {
+
+// The peak finder over a workspace of ws_cap bytes (0: the caller sized it
+// with find_peaks_workspace_bytes).
+dedisp_status find_peaks_impl(const void* in, dedisp_out_type in_type, int32_t ndm, int64_t nout,
+                              const int32_t* widths, int32_t nwidths, float snr_thresh,
+                              dedisp_event* events, int64_t capacity, int64_t* n_events,
+                              void* workspace, size_t ws_cap, hipStream_t stream) {
     if (!in || !n_events || !workspace || (capacity > 0 && !events))
         return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
     if (capacity < 0) return fail(DEDISP_ERR_INVALID_ARG, "capacity < 0");
@@ -262,6 +267,10 @@ extern "C" dedisp_status find_peaks(const void* in, dedisp_out_type in_type, int
     st = split_threshold(snr_thresh, &kmant, &kexp2);
     if (st != DEDISP_OK) return st;
     const dd::PeaksLayout lay = dd::peaks_layout(ndm, nout, W);
+    if (ws_cap && lay.bytes > ws_cap)
+        return fail(DEDISP_ERR_UNSUPPORTED,
+                    "%d series of %lld samples need %zu bytes of workspace; the static scratch "
+                    "holds %zu", ndm, static_cast<long long>(nout), lay.bytes, ws_cap);
     const dd::PeaksWs ws = dd::peaks_ws(workspace, lay);
     const int u16 = in_type == DEDISP_OUT_U16;
     DD_HIP(dd::launch_peaks_count(in, u16, ndm, nout, W, lay, ws, kmant, kexp2, stream));
@@ -278,6 +287,57 @@ extern "C" dedisp_status find_peaks(const void* in, dedisp_out_type in_type, int
                     static_cast<long long>(total), static_cast<long long>(capacity));
     dd::clear_error();
     return DEDISP_OK;
+}
+
+// Workspace of find_peaks_noalloc: a static device array, one per GPU the
+// library runs on (each holds it until the process ends).  Host code never
+// passes its name to a kernel: the name is a host-side stand-in; the device
+// address comes from hipGetSymbolAddress, taken once per device on the first
+// call with that device current.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxScratchDevices] = {};
+
+dedisp_status scratch_address(void** out) {
+    int dev = -1;
+    DD_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(DEDISP_ERR_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxScratchDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(DEDISP_ERR_HIP, "address of the static scratch on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return DEDISP_OK;
+}
+
+}  // namespace
+
+extern "C" dedisp_status find_peaks(const void* in, dedisp_out_type in_type, int32_t ndm,
+                                    int64_t nout, const int32_t* widths, int32_t nwidths,
+                                    float snr_thresh, dedisp_event* events, int64_t capacity,
+                                    int64_t* n_events, void* workspace, dedisp_stream stream) {
+    return find_peaks_impl(in, in_type, ndm, nout, widths, nwidths, snr_thresh, events, capacity,
+                           n_events, workspace, 0, stream);
+}
+
+extern "C" dedisp_status find_peaks_noalloc(const void* in, dedisp_out_type in_type, int32_t ndm,
+                                            int64_t nout, const int32_t* widths, int32_t nwidths,
+                                            float snr_thresh, dedisp_event* events,
+                                            int64_t capacity, int64_t* n_events,
+                                            dedisp_stream stream) {
+    void* ws = nullptr;
+    const dedisp_status st = scratch_address(&ws);
+    if (st != DEDISP_OK) return st;
+    return find_peaks_impl(in, in_type, ndm, nout, widths, nwidths, snr_thresh, events, capacity,
+                           n_events, ws, kScratchBytes, stream);
 }
 
 extern "C" dedisp_status find_peaks_read_stats(const void* workspace, int32_t ndm, int64_t nout,
