@@ -317,6 +317,26 @@ dedisp_status dedisp_batch_execute(dedisp_batch b, const uint8_t* const* in_2bit
 dedisp_status dedisp_batch_info(dedisp_batch b, dedisp_tile* tile, int32_t* grid,
                                 int32_t* captures);
 dedisp_status dedisp_batch_destroy(dedisp_batch b);
+/* Optional stages of the batch, in the order of the paper's pipeline
+ * (section 2: interference mitigation, dedispersion, baseline removal,
+ * matched filter, peak finding):
+ *   rfi_k_sigma > 0: the multibeam coincidence mask of section 2.1 (as
+ *     dedisp_rfi_mask with k_sigma and rfi_min_beams, over the samples every
+ *     beam has: 0 <= t < min_b nsamps_b) is applied before dedispersion --
+ *     flagged samples read as the mean level of every channel, as
+ *     dedisp_rfi_apply writes them; the caller's inputs are not modified.
+ *     Needs one channel count for all beams, 1 <= rfi_min_beams <= nbeams
+ *     <= 64.  rfi_k_sigma == 0: no mask.
+ *   baseline_radius R > 0 (<= 8192): baseline_remove of radius R (offset
+ *     3 nchans, the batch's series type; uint16 needs 6 nchans <= 65535)
+ *     runs between dedispersion and the search, which then covers the
+ *     nout - 2R samples of the flattened series: event times count from the
+ *     flattened series' first sample, dedispersed sample R.  0: none.
+ * `out` still receives the dedispersed series.  Takes effect at the next
+ * dedisp_batch_execute (the graph is captured again).  Errors: INVALID_ARG,
+ * UNSUPPORTED. */
+dedisp_status dedisp_batch_set_stages(dedisp_batch b, float rfi_k_sigma, int32_t rfi_min_beams,
+                                      int32_t baseline_radius);
 
 /* ------------------------------------------------------------------------
  * Autotuner of the dedispersion tile shape for one plan and input length.
@@ -420,6 +440,27 @@ dedisp_status dedisp_serve_stats(dedisp_server s, dedisp_serve_stats_t* stats);
  * and a 65536-record cluster buffer beyond the HBM budget given at create
  * (about 9 MB per slot at 1200 trials).  Errors: INVALID_ARG, BUSY,
  * OUT_OF_MEMORY. */
+/* Optional stages of every chunk, in the order of the paper's pipeline
+ * (section 2), set before the first submit (else BUSY):
+ *   rfi_k_sigma > 0: the multibeam coincidence mask of section 2.1 over the
+ *     round of chunks with one sequence number (as dedisp_rfi_mask with
+ *     k_sigma and rfi_min_beams, over each chunk's C new samples), applied to
+ *     those samples before dedispersion (dedisp_rfi_apply) -- the overlap a
+ *     window reuses was masked with its own round.  A round waits until every
+ *     beam has submitted that sequence number or a later one (a beam that
+ *     skipped it sits the round out) and runs when a slot is free for each of
+ *     its chunks, so the budget must hold a slot per beam.  rfi_k_sigma == 0:
+ *     no mask.
+ *   baseline_radius R > 0 (<= 8192, 6 nchans <= 65535): baseline_remove of
+ *     radius R (offset 3 nchans) between dedispersion and the search; the
+ *     overlap grows by 2R samples so that every chunk still yields C boxcar
+ *     positions, and t_abs0 is the absolute sample of the first position of
+ *     the flattened series (window start + R).  0: none.
+ * The chunk slots are sized again for the stages (the budget given at create
+ * still applies).  Errors: INVALID_ARG, UNSUPPORTED, BUSY, OUT_OF_MEMORY
+ * (the budget holds too few slots; the previous stages stay in force). */
+dedisp_status dedisp_serve_set_stages(dedisp_server s, float rfi_k_sigma, int32_t rfi_min_beams,
+                                      int32_t baseline_radius);
 dedisp_status dedisp_serve_set_clustering(dedisp_server s, int32_t dm_radius,
                                           int32_t width_radius, int64_t time_tol);
 dedisp_status dedisp_serve_destroy(dedisp_server s);

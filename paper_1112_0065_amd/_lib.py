@@ -112,6 +112,8 @@ def lib() -> C.CDLL:
         "dedisp_batch_create": (i32, [P(vp), i32, P(i32), i32, f32, i32, C.c_char_p, P(vp)]),
         "dedisp_batch_execute": (i32, [vp, P(vp), P(i64), P(vp), P(vp), P(i64), P(i64), vp]),
         "dedisp_batch_info": (i32, [vp, P(_Tile), P(i32), P(i32)]),
+        "dedisp_batch_set_stages": (i32, [vp, f32, i32, i32]),
+        "dedisp_serve_set_stages": (i32, [vp, f32, i32, i32]),
         "dedisp_batch_destroy": (i32, [vp]),
         "dedisp_autotune": (i32, [vp, i64, i32, C.c_char_p, P(_Tile), P(i32)]),
         "dedisp_rfi_mask_workspace_bytes": (sz, [i32, i64]),
@@ -612,6 +614,14 @@ def dedisp_batch_execute(batch: Batch, inputs, nsamps, outs, events, capacity, s
     return list(cnt)
 
 
+def dedisp_batch_set_stages(batch: Batch, rfi_k_sigma: float = 0.0, rfi_min_beams: int = 0,
+                            baseline_radius: int = 0):
+    """Coincidence mask before and baseline removal after dedispersion
+    (rfi_k_sigma 0 / radius 0 switch a stage off)."""
+    _check(lib().dedisp_batch_set_stages(batch.handle, float(rfi_k_sigma), int(rfi_min_beams),
+                                         int(baseline_radius)))
+
+
 def dedisp_batch_info(batch: Batch):
     t, g, c = _Tile(), C.c_int32(), C.c_int32()
     _check(lib().dedisp_batch_info(batch.handle, C.byref(t), C.byref(g), C.byref(c)))
@@ -705,6 +715,14 @@ def dedisp_serve_poll(server: Server, cap: int = 64, timeout_ms: int = 0):
                         arrival_ns=r.arrival_ns, done_ns=r.done_ns, flags=r.flags,
                         clusters=clusters, n_candidates=r.n_candidates))
     return out
+
+
+def dedisp_serve_set_stages(server, rfi_k_sigma: float = 0.0, rfi_min_beams: int = 0,
+                            baseline_radius: int = 0):
+    """Coincidence mask per round of chunks before, baseline removal after
+    dedispersion (0 switches a stage off).  Before the first submit."""
+    _check(lib().dedisp_serve_set_stages(server.handle, float(rfi_k_sigma), int(rfi_min_beams),
+                                         int(baseline_radius)))
 
 
 def dedisp_serve_set_clustering(server: Server, dm_radius: int, width_radius: int, time_tol: int):

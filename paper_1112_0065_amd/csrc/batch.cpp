@@ -6,6 +6,7 @@
 // The graph is re-captured whenever a beam's input, output, event buffer,
 // capacity or length changes.  Counters the persistent kernel pops work from
 // are cleared by a kernel inside the graph (no memset nodes).
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -36,6 +37,17 @@ struct dedisp_batch_s {
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // optional stages (dedisp_batch_set_stages)
+    int rfi_min = 0;                    // 0: no coincidence mask
+    uint32_t rfi_kmant = 0;
+    int rfi_kexp2 = 0;
+    int bl_radius = 0;                  // 0: no baseline removal
+    void* rfi_ws = nullptr;
+    size_t rfi_ws_bytes = 0;
+    void* d_mask = nullptr;
+    size_t mask_bytes = 0;
+    std::vector<void*> flat;
+    std::vector<size_t> flat_bytes;
     // capture key
     std::vector<const void*> k_in, k_out, k_ev;
     std::vector<int64_t> k_nsamps, k_cap;
@@ -50,7 +62,7 @@ namespace dd {
 hipError_t launch_multi(const MultiItem* items, int n, const Widths& W, uint32_t kmant, int kexp2,
                         int out_u16, const TileConfig& cfg, int nl, size_t lds, int grid, int nq,
                         BeamArgs* h_beams, BeamArgs* d_beams, unsigned long long* d_counters,
-                        hipStream_t s) {
+                        hipStream_t s, int bl_radius, int bl_offset) {
     int64_t total = 0;
     for (int i = 0; i < n; ++i) {
         const MultiItem& it = items[i];
@@ -64,19 +76,30 @@ hipError_t launch_multi(const MultiItem* items, int n, const Widths& W, uint32_t
     hipError_t e = hipMemcpyAsync(d_beams, h_beams, sizeof(BeamArgs) * n, hipMemcpyHostToDevice, s);
     for (int i = 0; i < n && e == hipSuccess; ++i)
         e = launch_repack(items[i].in, items[i].nsamps, items[i].plan->nchans,
-                          static_cast<uint2*>(items[i].words), repack_words(items[i].nsamps), s);
+                          static_cast<uint2*>(items[i].words), repack_words(items[i].nsamps), s,
+                          items[i].mask, items[i].mask_n);
     if (e == hipSuccess)
         e = launch_dedisperse_persistent(d_beams, n, total, nl, out_u16, cfg, lds, d_counters, nq,
                                          grid, s);
     for (int i = 0; i < n && e == hipSuccess; ++i) {
         const MultiItem& it = items[i];
         const dedisp_plan_s* p = it.plan;
-        const int64_t nout = it.nsamps - p->max_delay;
+        int64_t nout = it.nsamps - p->max_delay;
+        const void* series = it.out;
+        if (it.flat) {
+            // baseline removal between dedispersion and the search: the
+            // search runs on the nout - 2R samples of the flattened series
+            e = launch_baseline(it.out, out_u16, p->ndm, nout, bl_radius, bl_offset, it.flat,
+                                out_u16, s);
+            if (e != hipSuccess) break;
+            series = it.flat;
+            nout -= 2 * static_cast<int64_t>(bl_radius);
+        }
         const PeaksLayout lay = peaks_layout(p->ndm, nout, W);
         const PeaksWs ws = peaks_ws(it.pk_ws, lay);
-        e = launch_peaks_count(it.out, out_u16, p->ndm, nout, W, lay, ws, kmant, kexp2, s);
+        e = launch_peaks_count(series, out_u16, p->ndm, nout, W, lay, ws, kmant, kexp2, s);
         if (e == hipSuccess && it.capacity > 0)
-            e = launch_peaks_write(it.out, out_u16, p->ndm, nout, W, lay, ws, it.events, it.capacity, s);
+            e = launch_peaks_write(series, out_u16, p->ndm, nout, W, lay, ws, it.events, it.capacity, s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(it.h_total, ws.total, sizeof(int64_t), hipMemcpyDeviceToHost, s);
     }
@@ -173,6 +196,8 @@ extern "C" dedisp_status dedisp_batch_create(const dedisp_plan* plans, int32_t n
     hipError_t e = hipSuccess;
     b->words.assign(nbeams, nullptr);
     b->pk_ws.assign(nbeams, nullptr);
+    b->flat.assign(nbeams, nullptr);
+    b->flat_bytes.assign(nbeams, 0);
     b->words_bytes.assign(nbeams, 0);
     b->pk_bytes.assign(nbeams, 0);
     e = hipMalloc(&b->d_beams, sizeof(dd::BeamArgs) * nbeams);
@@ -197,6 +222,10 @@ extern "C" dedisp_status dedisp_batch_destroy(dedisp_batch b) {
         if (p) (void)hipFree(p);
     for (void* p : b->pk_ws)
         if (p) (void)hipFree(p);
+    for (void* p : b->flat)
+        if (p) (void)hipFree(p);
+    if (b->rfi_ws) (void)hipFree(b->rfi_ws);
+    if (b->d_mask) (void)hipFree(b->d_mask);
     if (b->d_beams) (void)hipFree(b->d_beams);
     if (b->d_counters) (void)hipFree(b->d_counters);
     if (b->h_totals) (void)hipHostFree(b->h_totals);
@@ -215,19 +244,59 @@ extern "C" dedisp_status dedisp_batch_info(dedisp_batch b, dedisp_tile* tile, in
     return DEDISP_OK;
 }
 
+extern "C" dedisp_status dedisp_batch_set_stages(dedisp_batch b, float rfi_k_sigma,
+                                                 int32_t rfi_min_beams, int32_t baseline_radius) {
+    if (!b) return fail(DEDISP_ERR_INVALID_ARG, "batch is NULL");
+    uint32_t km = 0;
+    int ke = 0;
+    if (rfi_k_sigma != 0.0f) {
+        dedisp_status st = dd::split_threshold_public(rfi_k_sigma, &km, &ke);
+        if (st != DEDISP_OK) return st;
+        if (rfi_min_beams < 1 || rfi_min_beams > b->nbeams || b->nbeams > 64)
+            return fail(DEDISP_ERR_INVALID_ARG, "min_beams %d outside [1, %d] (at most 64 beams)",
+                        rfi_min_beams, b->nbeams);
+        for (int i = 1; i < b->nbeams; ++i)
+            if (b->plans[i]->nchans != b->plans[0]->nchans)
+                return fail(DEDISP_ERR_INVALID_ARG, "the coincidence mask needs one channel count");
+    }
+    if (baseline_radius < 0 || baseline_radius > 8192)
+        return fail(DEDISP_ERR_INVALID_ARG, "baseline radius %d outside [0, 8192]", baseline_radius);
+    if (baseline_radius > 0)
+        for (int i = 0; i < b->nbeams; ++i)
+            if (b->out_u16 && 6 * b->plans[i]->nchans > 65535)
+                return fail(DEDISP_ERR_UNSUPPORTED, "uint16 baseline output needs 6 nchans <= 65535");
+    b->rfi_min = rfi_k_sigma != 0.0f ? rfi_min_beams : 0;
+    b->rfi_kmant = km;
+    b->rfi_kexp2 = ke;
+    b->bl_radius = baseline_radius;
+    release_graph(b);   // the next execute captures the new sequence
+    dd::clear_error();
+    return DEDISP_OK;
+}
+
 namespace {
 
 dedisp_status capture(dedisp_batch_s* b, const uint8_t* const* in, const int64_t* nsamps,
                       void* const* out, dedisp_event* const* events, const int64_t* capacity) {
     release_graph(b);
+    int64_t n_common = nsamps[0];
+    for (int i = 1; i < b->nbeams; ++i) n_common = std::min(n_common, nsamps[i]);
+    const uint8_t* mask = b->rfi_min ? static_cast<const uint8_t*>(b->d_mask) : nullptr;
     std::vector<dd::MultiItem> items(b->nbeams);
     for (int i = 0; i < b->nbeams; ++i)
         items[i] = dd::MultiItem{b->plans[i], in[i], nsamps[i], b->words[i], out[i], b->pk_ws[i],
-                                 events[i], capacity[i], &b->h_totals[i]};
+                                 events[i], capacity[i], &b->h_totals[i], mask, n_common,
+                                 b->bl_radius ? b->flat[i] : nullptr};
     DD_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-    const hipError_t e = dd::launch_multi(items.data(), b->nbeams, b->W, b->kmant, b->kexp2, b->out_u16,
-                                          b->cfg, b->nl, b->lds, b->grid, b->nq, b->h_beams, b->d_beams,
-                                          b->d_counters, b->cap);
+    hipError_t e = hipSuccess;
+    if (mask)
+        e = dd::launch_rfi_mask(in, b->nbeams, b->plans[0]->nchans, n_common, b->rfi_kmant,
+                                b->rfi_kexp2, b->rfi_min, static_cast<uint8_t*>(b->d_mask),
+                                b->rfi_ws, b->cap);
+    if (e == hipSuccess)
+        e = dd::launch_multi(items.data(), b->nbeams, b->W, b->kmant, b->kexp2, b->out_u16, b->cfg,
+                             b->nl, b->lds, b->grid, b->nq, b->h_beams, b->d_beams, b->d_counters,
+                             b->cap, b->bl_radius, 3 * b->plans[0]->nchans);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(b->cap, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -254,7 +323,7 @@ extern "C" dedisp_status dedisp_batch_execute(dedisp_batch b, const uint8_t* con
         const dedisp_plan_s* p = b->plans[i];
         if (!in_2bit[i] || !out[i] || capacity[i] < 0 || (capacity[i] > 0 && !events[i]))
             return fail(DEDISP_ERR_INVALID_ARG, "beam %d: NULL buffer or negative capacity", i);
-        if (nsamps[i] - p->max_delay - w_max + 1 < 1)
+        if (nsamps[i] - p->max_delay - 2 * static_cast<int64_t>(b->bl_radius) - w_max + 1 < 1)
             return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "beam %d: %lld samples", i,
                         static_cast<long long>(nsamps[i]));
         if ((nsamps[i] - p->max_delay + 16384 + w_max) * 4 >= (int64_t(1) << 31))
@@ -271,7 +340,21 @@ extern "C" dedisp_status dedisp_batch_execute(dedisp_batch b, const uint8_t* con
             dedisp_status st = ensure(b->words[i], b->words_bytes[i],
                                       static_cast<size_t>(p->nchans) * dd::repack_words(nsamps[i]) * sizeof(uint2));
             if (st != DEDISP_OK) return st;
-            st = ensure(b->pk_ws[i], b->pk_bytes[i], dd::peaks_layout(p->ndm, nout, b->W).bytes);
+            const int64_t nsearch = nout - 2 * static_cast<int64_t>(b->bl_radius);
+            st = ensure(b->pk_ws[i], b->pk_bytes[i], dd::peaks_layout(p->ndm, nsearch, b->W).bytes);
+            if (st != DEDISP_OK) return st;
+            if (b->bl_radius) {
+                st = ensure(b->flat[i], b->flat_bytes[i],
+                            static_cast<size_t>(p->ndm) * nsearch * (b->out_u16 ? 2 : 4));
+                if (st != DEDISP_OK) return st;
+            }
+        }
+        if (b->rfi_min) {
+            int64_t n_common = nsamps[0];
+            for (int i = 1; i < b->nbeams; ++i) n_common = std::min(n_common, nsamps[i]);
+            dedisp_status st = ensure(b->rfi_ws, b->rfi_ws_bytes, dd::rfi_mask_ws_bytes(b->nbeams, n_common));
+            if (st != DEDISP_OK) return st;
+            st = ensure(b->d_mask, b->mask_bytes, static_cast<size_t>(n_common));
             if (st != DEDISP_OK) return st;
         }
         dedisp_status st = capture(b, in_2bit, nsamps, out, events, capacity);

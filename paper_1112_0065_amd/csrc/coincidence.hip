@@ -214,6 +214,61 @@ __global__ __launch_bounds__(kCThreads) void rfi_apply_kernel(BeamPtrs beams, in
 
 }  // namespace
 
+namespace dd {
+
+size_t rfi_mask_ws_bytes(int nbeams, int64_t nsamps) { return coinc_layout(nbeams, nsamps).bytes; }
+
+hipError_t launch_rfi_mask(const uint8_t* const* ins, int nbeams, int nchans, int64_t nsamps,
+                           uint32_t kmant, int kexp2, int min_beams, uint8_t* mask, void* workspace,
+                           hipStream_t stream) {
+    const CoincLayout l = coinc_layout(nbeams, nsamps);
+    char* w = static_cast<char*>(workspace);
+    int32_t* z = reinterpret_cast<int32_t*>(w + l.o_z);
+    uint64_t* p1 = reinterpret_cast<uint64_t*>(w + l.o_p1);
+    uint64_t* p2 = reinterpret_cast<uint64_t*>(w + l.o_p2);
+    int64_t* thr = reinterpret_cast<int64_t*>(w + l.o_thr);
+    unsigned long long* count = reinterpret_cast<unsigned long long*>(w + l.o_count);
+    const int bps = nchans / 4;
+    for (int b = 0; b < nbeams; ++b) {
+        int32_t* zb = z + static_cast<int64_t>(b) * nsamps;
+        if (bps == 256 && (reinterpret_cast<uintptr_t>(ins[b]) & 15) == 0) {
+            const int64_t waves = std::min<int64_t>((nsamps + 3) / 4, 256 * 64);
+            hipLaunchKernelGGL(zero_dm_256_kernel, dim3(static_cast<unsigned>((waves + 3) / 4)),
+                               dim3(kCThreads), 0, stream, ins[b], nsamps, zb);
+        } else {
+            hipLaunchKernelGGL(zero_dm_any_kernel,
+                               dim3(static_cast<unsigned>((nsamps + kCThreads - 1) / kCThreads)),
+                               dim3(kCThreads), 0, stream, ins[b], nsamps, bps, zb);
+        }
+    }
+    hipLaunchKernelGGL(zero_dm_stats_kernel, dim3(l.nblk, nbeams), dim3(kCThreads), 0, stream, z,
+                       nsamps, l.nblk, p1, p2);
+    hipLaunchKernelGGL(zero_dm_threshold_kernel, dim3(1), dim3(64), 0, stream, nbeams, l.nblk,
+                       nsamps, kmant, kexp2, p1, p2, thr, count);
+    hipLaunchKernelGGL(coincidence_vote_kernel,
+                       dim3(static_cast<unsigned>((nsamps + kCThreads - 1) / kCThreads)),
+                       dim3(kCThreads), 0, stream, z, nsamps, nbeams, min_beams, thr, mask, count);
+    return hipGetLastError();
+}
+
+const unsigned long long* rfi_mask_count(const void* workspace, int nbeams, int64_t nsamps) {
+    return reinterpret_cast<const unsigned long long*>(static_cast<const char*>(workspace) +
+                                                       coinc_layout(nbeams, nsamps).o_count);
+}
+
+hipError_t launch_rfi_apply(uint8_t* const* beams, int nbeams, int nchans, int64_t nsamps,
+                            const uint8_t* mask, hipStream_t stream) {
+    if (nbeams < 1 || nbeams > 64) return hipErrorInvalidValue;
+    BeamPtrs ptrs{};
+    for (int b = 0; b < nbeams; ++b) ptrs.p[b] = beams[b];
+    const int64_t n = nsamps * nbeams;
+    hipLaunchKernelGGL(rfi_apply_kernel, dim3(static_cast<unsigned>((n + kCThreads - 1) / kCThreads)),
+                       dim3(kCThreads), 0, stream, ptrs, nbeams, nsamps, nchans / 4, mask);
+    return hipGetLastError();
+}
+
+}  // namespace dd
+
 extern "C" size_t dedisp_rfi_mask_workspace_bytes(int32_t nbeams, int64_t nsamps) {
     if (nbeams < 1 || nbeams > 64 || nsamps < 1 || nsamps >= (int64_t(1) << 31)) return 0;
     return coinc_layout(nbeams, nsamps).bytes;
@@ -238,36 +293,11 @@ extern "C" dedisp_status dedisp_rfi_mask(const uint8_t* const* in_2bit, int32_t 
     int kexp2 = 0;
     dedisp_status st = dd::split_threshold_public(k_sigma, &kmant, &kexp2);
     if (st != DEDISP_OK) return st;
-    const CoincLayout l = coinc_layout(nbeams, nsamps);
-    char* w = static_cast<char*>(workspace);
-    int32_t* z = reinterpret_cast<int32_t*>(w + l.o_z);
-    uint64_t* p1 = reinterpret_cast<uint64_t*>(w + l.o_p1);
-    uint64_t* p2 = reinterpret_cast<uint64_t*>(w + l.o_p2);
-    int64_t* thr = reinterpret_cast<int64_t*>(w + l.o_thr);
-    unsigned long long* count = reinterpret_cast<unsigned long long*>(w + l.o_count);
-    const int bps = nchans / 4;
-    for (int b = 0; b < nbeams; ++b) {
-        int32_t* zb = z + static_cast<int64_t>(b) * nsamps;
-        if (bps == 256 && (reinterpret_cast<uintptr_t>(in_2bit[b]) & 15) == 0) {
-            const int64_t waves = std::min<int64_t>((nsamps + 3) / 4, 256 * 64);
-            hipLaunchKernelGGL(zero_dm_256_kernel, dim3(static_cast<unsigned>((waves + 3) / 4)),
-                               dim3(kCThreads), 0, stream, in_2bit[b], nsamps, zb);
-        } else {
-            hipLaunchKernelGGL(zero_dm_any_kernel,
-                               dim3(static_cast<unsigned>((nsamps + kCThreads - 1) / kCThreads)),
-                               dim3(kCThreads), 0, stream, in_2bit[b], nsamps, bps, zb);
-        }
-    }
-    hipLaunchKernelGGL(zero_dm_stats_kernel, dim3(l.nblk, nbeams), dim3(kCThreads), 0, stream, z,
-                       nsamps, l.nblk, p1, p2);
-    hipLaunchKernelGGL(zero_dm_threshold_kernel, dim3(1), dim3(64), 0, stream, nbeams, l.nblk,
-                       nsamps, kmant, kexp2, p1, p2, thr, count);
-    hipLaunchKernelGGL(coincidence_vote_kernel,
-                       dim3(static_cast<unsigned>((nsamps + kCThreads - 1) / kCThreads)),
-                       dim3(kCThreads), 0, stream, z, nsamps, nbeams, min_beams, thr, mask, count);
-    DD_HIP(hipGetLastError());
+    DD_HIP(dd::launch_rfi_mask(in_2bit, nbeams, nchans, nsamps, kmant, kexp2, min_beams, mask,
+                               workspace, stream));
     unsigned long long total = 0;
-    DD_HIP(hipMemcpyAsync(&total, count, sizeof total, hipMemcpyDeviceToHost, stream));
+    DD_HIP(hipMemcpyAsync(&total, dd::rfi_mask_count(workspace, nbeams, nsamps), sizeof total,
+                          hipMemcpyDeviceToHost, stream));
     DD_HIP(hipStreamSynchronize(stream));
     *n_masked = static_cast<int64_t>(total);
     dd::clear_error();
@@ -300,15 +330,9 @@ extern "C" dedisp_status dedisp_rfi_apply(uint8_t* const* beams_2bit, int32_t nb
     if (!coinc_args_ok(nbeams, nchans, nsamps))
         return fail(DEDISP_ERR_INVALID_ARG,
                     "need 1 <= nbeams <= 64, nchans a multiple of 4 in [4, 21844], 1 <= nsamps < 2^31");
-    BeamPtrs ptrs{};
-    for (int b = 0; b < nbeams; ++b) {
+    for (int b = 0; b < nbeams; ++b)
         if (!beams_2bit[b]) return fail(DEDISP_ERR_INVALID_ARG, "beam %d is NULL", b);
-        ptrs.p[b] = beams_2bit[b];
-    }
-    const int64_t n = nsamps * nbeams;
-    hipLaunchKernelGGL(rfi_apply_kernel, dim3(static_cast<unsigned>((n + kCThreads - 1) / kCThreads)),
-                       dim3(kCThreads), 0, stream, ptrs, nbeams, nsamps, nchans / 4, mask);
-    DD_HIP(hipGetLastError());
+    DD_HIP(dd::launch_rfi_apply(beams_2bit, nbeams, nchans, nsamps, mask, stream));
     dd::clear_error();
     return DEDISP_OK;
 }

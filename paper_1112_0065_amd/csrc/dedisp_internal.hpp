@@ -100,7 +100,8 @@ inline int dm_block_index(int dms_per_block) {
 
 // Kernel launchers (asynchronous; return hipError_t of the launch).
 hipError_t launch_repack(const uint8_t* in, int64_t nsamps, int nchans, uint2* words,
-                         int64_t nwords, hipStream_t s);
+                         int64_t nwords, hipStream_t s, const uint8_t* mask = nullptr,
+                         int64_t mask_n = 0);
 dedisp_status launch_dedisperse(const dedisp_plan_s* p, const uint2* words,
                                 int64_t nwords, int64_t nout, void* out, int out_u16,
                                 const TileConfig& cfg, hipStream_t s);
@@ -138,6 +139,9 @@ struct MultiItem {
     dedisp_event* events;   // device, capacity records
     int64_t capacity;
     int64_t* h_total;       // pinned host: number of events found
+    const uint8_t* mask;    // device coincidence mask of samples [0, mask_n), or NULL
+    int64_t mask_n;
+    void* flat;             // device [ndm][nout - 2R] baseline-removed series, or NULL
 };
 // Persistent grid size for this shape on `device` (multiple of nq; 0 on error).
 int batch_grid(int nl, int out_u16, const TileConfig& cfg, size_t lds, int device, int nq);

@@ -6,7 +6,8 @@
 //         t*nchans/4 + c/4.
 // Output: words[c*nwords + j] = {lo, hi}: bit b of lo/hi is bit 0/1 of the
 //         level of sample 32j+b of channel c.  Samples >= nsamps and the two
-//         trailing words are zero.
+//         trailing words are zero.  With a coincidence mask, samples t < mask_n
+//         with mask[t] != 0 are read as the mean level of every channel.
 //
 // One block covers a tile of 512 samples x 256 channels (64 bytes per input
 // row, 16 output words per channel).  The input rows are staged in LDS with
@@ -47,7 +48,8 @@ __global__ __launch_bounds__(256) void repack_2bit_kernel(const uint8_t* __restr
                                                           int64_t nsamps, int nchans,
                                                           uint2* __restrict__ words,
                                                           int64_t nwords, int64_t ntiles, int vec16,
-                                                          int st16) {
+                                                          int st16, const uint8_t* __restrict__ mask,
+                                                          int64_t mask_n) {
     // the input tile, then (after every wave holds its words) the output tile
     __shared__ uint32_t buf[kBufWords];
     const int tid = threadIdx.x;
@@ -71,6 +73,14 @@ __global__ __launch_bounds__(256) void repack_2bit_kernel(const uint8_t* __restr
                 v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
             } else {
                 for (int i = 0; i < nb; ++i) v[i >> 2] |= static_cast<uint32_t>(src[i]) << (8 * (i & 3));
+            }
+            // a flagged sample reads as the mean level in every channel
+            // (byte 0x99: levels 1, 2, 1, 2), as the coincidence mask's
+            // application writes it
+            if (mask && t < mask_n && mask[t]) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = 0u;
+                for (int i = 0; i < nb; ++i) v[i >> 2] |= 0x99u << (8 * (i & 3));
             }
         }
 #pragma unroll
@@ -136,7 +146,7 @@ namespace dd {
 // Tiles cover the words, the two trailing ones included: every word of every
 // channel row is written once (zeros past the last sample).
 hipError_t launch_repack(const uint8_t* in, int64_t nsamps, int nchans, uint2* words,
-                         int64_t nwords, hipStream_t s) {
+                         int64_t nwords, hipStream_t s, const uint8_t* mask, int64_t mask_n) {
     if (nwords != repack_words(nsamps) || nwords % 2) return hipErrorInvalidValue;
     const int64_t tiles_t = (nwords + kTileW - 1) / kTileW;
     const dim3 grid(static_cast<unsigned>((nchans + kTileC - 1) / kTileC),
@@ -144,7 +154,7 @@ hipError_t launch_repack(const uint8_t* in, int64_t nsamps, int nchans, uint2* w
     const int vec16 = ((nchans >> 2) % 16 == 0) && (reinterpret_cast<uintptr_t>(in) % 16 == 0);
     const int st16 = reinterpret_cast<uintptr_t>(words) % 16 == 0;
     hipLaunchKernelGGL(repack_2bit_kernel, grid, dim3(256), 0, s, in, nsamps, nchans, words,
-                       nwords, tiles_t, vec16, st16);
+                       nwords, tiles_t, vec16, st16, mask, mask ? mask_n : 0);
     return hipGetLastError();
 }
 

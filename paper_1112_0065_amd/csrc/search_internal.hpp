@@ -78,11 +78,22 @@ hipError_t launch_peaks_write(const void* in, int in_u16, int ndm, int64_t nout,
                               const PeaksLayout& lay, const PeaksWs& ws, dedisp_event* events,
                               int64_t capacity, hipStream_t s);
 
-// Shared by the batch and the streaming server: see batch.cpp.
+// Shared by the batch and the streaming server: see batch.cpp.  Items with a
+// mask read flagged samples as the mean level; items with a `flat` buffer get
+// baseline removal of radius bl_radius (offset bl_offset) before the search.
 hipError_t launch_multi(const MultiItem* items, int n, const Widths& W, uint32_t kmant, int kexp2,
                         int out_u16, const TileConfig& cfg, int nl, size_t lds, int grid, int nq,
                         BeamArgs* h_beams, BeamArgs* d_beams, unsigned long long* d_counters,
-                        hipStream_t s);
+                        hipStream_t s, int bl_radius = 0, int bl_offset = 0);
+// Coincidence mask (coincidence.hip): asynchronous, the number of flagged
+// samples left on the device (rfi_mask_count); workspace rfi_mask_ws_bytes.
+size_t rfi_mask_ws_bytes(int nbeams, int64_t nsamps);
+hipError_t launch_rfi_mask(const uint8_t* const* ins, int nbeams, int nchans, int64_t nsamps,
+                           uint32_t kmant, int kexp2, int min_beams, uint8_t* mask, void* workspace,
+                           hipStream_t stream);
+const unsigned long long* rfi_mask_count(const void* workspace, int nbeams, int64_t nsamps);
+hipError_t launch_rfi_apply(uint8_t* const* beams, int nbeams, int nchans, int64_t nsamps,
+                            const uint8_t* mask, hipStream_t stream);
 dedisp_status split_threshold_public(float k, uint32_t* kmant, int* kexp2);
 dedisp_status check_widths_public(const int32_t* widths, int32_t nwidths, int64_t nout, Widths* W);
 TileConfig tuned_or_default(const dedisp_plan_s* p, const char* cache_path, int out_u16);

@@ -21,6 +21,7 @@
 // records latency, frees slots).
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
@@ -56,6 +57,7 @@ struct Slot {
     dedisp_event* d_cand = nullptr;     // the events triage scores (after selection)
     void* cl_ws = nullptr;              // clustering workspace (when enabled)
     dedisp_cluster* d_clusters = nullptr;
+    void* flat = nullptr;               // baseline-removed series (when that stage is on)
     bool busy = false;
 };
 
@@ -107,6 +109,15 @@ struct dedisp_server_s {
     float triage_thresh = 0.5f;
     double deadline_ns = 0;
     int64_t ndm_max = 0;
+    size_t budget = 0;             // HBM budget of the overlaps and chunk slots
+    bool draining = false;         // destroy: release incomplete rounds
+    // optional stages (dedisp_serve_set_stages)
+    int bl_radius = 0;             // baseline removal radius, 0 = off
+    int rfi_min = 0;               // coincidence mask: min beams, 0 = off
+    uint32_t rfi_kmant = 0;
+    int rfi_kexp2 = 0;
+    void* rfi_ws = nullptr;        // mask workspace and mask of one round (copy stream)
+    uint8_t* d_mask = nullptr;
     // clustering of each chunk's events (dedisp_serve_set_clustering)
     bool cluster_on = false;
     int32_t cl_dm_radius = 0, cl_width_radius = 0;
@@ -126,6 +137,7 @@ struct dedisp_server_s {
 
     // per-beam stream state (scheduler side)
     std::vector<int64_t> next_seq;       // expected next sequence number (submit side)
+    int submitting = 0;                  // submits between admission and the pending queue
     std::vector<bool> have_overlap;
 
     // queues
@@ -178,11 +190,48 @@ hipError_t assemble(dedisp_server_s* s, Job& j) {
         e = hipMemcpyAsync(sl.window + off * bpc, s->host_bufs[j.host_buf], s->C * bpc,
                            hipMemcpyHostToDevice, s->copy_s);
     j.nsamps = off + s->C;
-    // new overlap: the window's last H_b samples
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(s->overlap[j.beam], sl.window + (j.nsamps - Hb) * bpc, Hb * bpc,
-                           hipMemcpyDeviceToDevice, s->copy_s);
     return e;
+}
+
+// Save the window's last H_b samples as the beam's next overlap.
+hipError_t save_overlap(dedisp_server_s* s, const Job& j) {
+    const int64_t bpc = s->nchans / 4;
+    const int64_t Hb = s->Hb[j.beam];
+    return hipMemcpyAsync(s->overlap[j.beam], s->slots[j.slot].window + (j.nsamps - Hb) * bpc,
+                          Hb * bpc, hipMemcpyDeviceToDevice, s->copy_s);
+}
+
+// Coincidence mask of one round: the new C samples of every job's window
+// (the overlaps were masked with their own round), applied in place before
+// the overlaps are saved.  On copy_s, in stream order with the assembly.
+hipError_t mask_round(dedisp_server_s* s, const std::vector<Job>& round) {
+    const int64_t bpc = s->nchans / 4;
+    std::vector<uint8_t*> news;
+    for (const Job& j : round) news.push_back(s->slots[j.slot].window + (j.nsamps - s->C) * bpc);
+    const int n = static_cast<int>(news.size());
+    std::vector<const uint8_t*> cnews(news.begin(), news.end());
+    hipError_t e = dd::launch_rfi_mask(cnews.data(), n, s->nchans, s->C, s->rfi_kmant, s->rfi_kexp2,
+                                       s->rfi_min, s->d_mask, s->rfi_ws, s->copy_s);
+    if (e == hipSuccess) e = dd::launch_rfi_apply(news.data(), n, s->nchans, s->C, s->d_mask, s->copy_s);
+    return e;
+}
+
+// With the coincidence mask: is the round of the lowest pending sequence
+// number k ready -- every beam has submitted k or a later chunk (a beam that
+// skipped k sits the round out) and a slot is free for each of the round's
+// chunks?  Called with s->mu held.
+bool round_ready(const dedisp_server_s* s, int64_t* k_out) {
+    int64_t k = INT64_MAX;
+    for (const Job& j : s->pending) k = std::min(k, j.seq);
+    if (k == INT64_MAX) return false;
+    if (s->submitting > 0 && !s->draining) return false;   // a chunk of the round may be on its way
+    for (int64_t q : s->next_seq)
+        if (q <= k && !s->draining) return false;
+    size_t nfree = 0, nk = 0;
+    for (const Slot& sl : s->slots) nfree += sl.busy ? 0 : 1;
+    for (const Job& j : s->pending) nk += j.seq == k ? 1 : 0;
+    if (k_out) *k_out = k;
+    return nk <= nfree;
 }
 
 void scheduler(dedisp_server_s* s) {
@@ -197,16 +246,41 @@ void scheduler(dedisp_server_s* s) {
             s->cv_sched.wait(lk, [&] {
                 if (s->stop) return true;
                 if (s->pending.empty() || s->ring_used >= dedisp_server_s::kRing) return false;
+                if (s->rfi_min) return round_ready(s, nullptr);
                 for (const Slot& sl : s->slots)
                     if (!sl.busy) return true;
                 return false;
             });
             if (s->stop) break;
-            // every pending chunk (any beam, in arrival order) while slots last
-            for (size_t i = 0; i < s->slots.size() && !s->pending.empty(); ++i) {
+            // with the coincidence mask, whole rounds only: the pending
+            // chunks of the lowest sequence number, once every beam has
+            // submitted it (or passed it: a gap), and only when a slot is
+            // free for each of them
+            std::vector<Job> round;
+            if (s->rfi_min) {
+                int64_t k = 0;
+                round_ready(s, &k);
+                for (auto it = s->pending.begin(); it != s->pending.end();) {
+                    if (it->seq == k) {
+                        round.push_back(*it);
+                        it = s->pending.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+            }
+            // every pending chunk (any beam, in arrival order) while slots
+            // last, or the round
+            for (size_t i = 0; i < s->slots.size() && (s->rfi_min ? !round.empty() : !s->pending.empty()); ++i) {
                 if (s->slots[i].busy) continue;
-                Job j = s->pending.front();
-                s->pending.pop_front();
+                Job j;
+                if (s->rfi_min) {
+                    j = round.front();
+                    round.erase(round.begin());
+                } else {
+                    j = s->pending.front();
+                    s->pending.pop_front();
+                }
                 s->slots[i].busy = true;
                 j.slot = static_cast<int>(i);
                 j.h_total = &s->h_totals[i];
@@ -221,20 +295,36 @@ void scheduler(dedisp_server_s* s) {
             s->ring_used++;
         }
         hipError_t e = hipSuccess;
-        for (Job& j : take)
-            if (e == hipSuccess) e = assemble(s, j);
+        if (s->rfi_min) {
+            // one chunk per beam: every window, then the round's mask, then
+            // the (masked) overlaps
+            for (Job& j : take)
+                if (e == hipSuccess) e = assemble(s, j);
+            if (e == hipSuccess) e = mask_round(s, take);
+            for (Job& j : take)
+                if (e == hipSuccess) e = save_overlap(s, j);
+        } else {
+            // a batch may hold consecutive chunks of one beam: each window
+            // takes the overlap its predecessor just saved
+            for (Job& j : take) {
+                if (e == hipSuccess) e = assemble(s, j);
+                if (e == hipSuccess) e = save_overlap(s, j);
+            }
+        }
         if (e == hipSuccess) e = hipEventRecord(copied, s->copy_s);
         if (e == hipSuccess) e = hipStreamWaitEvent(s->comp_s, copied, 0);
         std::vector<dd::MultiItem> items(take.size());
         for (size_t i = 0; i < take.size(); ++i) {
             const Slot& sl = s->slots[take[i].slot];
             items[i] = dd::MultiItem{s->plans[take[i].beam], sl.window, take[i].nsamps, sl.words, sl.out,
-                                     sl.pk_ws, sl.d_events, s->capacity, take[i].h_total};
+                                     sl.pk_ws, sl.d_events, s->capacity, take[i].h_total, nullptr, 0,
+                                     s->bl_radius ? sl.flat : nullptr};
         }
         if (e == hipSuccess)
             e = dd::launch_multi(items.data(), static_cast<int>(items.size()), s->W, s->kmant, s->kexp2, 1,
                                  s->cfg, s->nl, s->lds, s->grid, s->nq, s->h_beams[ring],
-                                 s->d_beams[ring], s->d_counters, s->comp_s);
+                                 s->d_beams[ring], s->d_counters, s->comp_s, s->bl_radius,
+                                 3 * s->nchans);
         Batch b;
         b.jobs = std::move(take);
         b.ring = ring;
@@ -314,8 +404,9 @@ void completer(dedisp_server_s* s) {
                 // non-maximum suppression keeps (the selection it was trained
                 // on); suppressed events get no score (-1)
                 const dedisp_plan_s* p = s->plans[j.beam];
-                const int64_t nout = j.nsamps - p->max_delay;
+                const int64_t nout = j.nsamps - p->max_delay - 2 * static_cast<int64_t>(s->bl_radius);
                 const Slot& sl = s->slots[j.slot];
+                const void* series = s->bl_radius ? sl.flat : sl.out;
                 std::vector<int64_t> keep(static_cast<size_t>(std::max<int64_t>(m, 1)));
                 int64_t nk = 0;
                 dedisp_status tst = dedisp_candidates_nms(r.events.data(), m, s->W.w, s->W.n, 32, 128,
@@ -329,7 +420,7 @@ void completer(dedisp_server_s* s) {
                 }
                 std::vector<float> cs;
                 if (tst == DEDISP_OK)
-                    tst = dd::triage_score_events(s->model, sl.out, sl.pk_ws, p->ndm, nout, s->W, sl.d_cand,
+                    tst = dd::triage_score_events(s->model, series, sl.pk_ws, p->ndm, nout, s->W, sl.d_cand,
                                                   nk, &cs, s->done_s);
                 if (tst == DEDISP_OK) {
                     r.scores.assign(static_cast<size_t>(m), -1.0f);
@@ -343,8 +434,11 @@ void completer(dedisp_server_s* s) {
             }
             r.r.beam = j.beam;
             r.r.seq = j.seq;
-            r.r.t_abs0 = j.t_abs0;
-            r.r.n_bx = j.nsamps - s->plans[j.beam]->max_delay - s->W.w[s->W.n - 1] + 1;
+            // with baseline removal the search covers the flattened series,
+            // which starts at dedispersed sample R of the window
+            r.r.t_abs0 = j.t_abs0 + s->bl_radius;
+            r.r.n_bx = j.nsamps - s->plans[j.beam]->max_delay - 2 * static_cast<int64_t>(s->bl_radius) -
+                       s->W.w[s->W.n - 1] + 1;
             r.r.n_events = n;
             r.r.arrival_ns = j.arrival_ns;
             r.r.done_ns = now_ns();
@@ -374,9 +468,12 @@ void completer(dedisp_server_s* s) {
     }
 }
 
-void free_server(dedisp_server_s* s) {
+// Device and pinned buffers sized by the chunk, the stages and the budget
+// (not the streams or threads).
+void free_buffers(dedisp_server_s* s) {
     for (uint8_t* p : s->overlap)
         if (p) (void)hipFree(p);
+    s->overlap.clear();
     for (Slot& sl : s->slots) {
         if (sl.window) (void)hipFree(sl.window);
         if (sl.words) (void)hipFree(sl.words);
@@ -386,19 +483,130 @@ void free_server(dedisp_server_s* s) {
         if (sl.d_cand) (void)hipFree(sl.d_cand);
         if (sl.cl_ws) (void)hipFree(sl.cl_ws);
         if (sl.d_clusters) (void)hipFree(sl.d_clusters);
+        if (sl.flat) (void)hipFree(sl.flat);
     }
+    s->slots.clear();
     for (int i = 0; i < dedisp_server_s::kRing; ++i) {
         if (s->h_beams[i]) (void)hipHostFree(s->h_beams[i]);
         if (s->d_beams[i]) (void)hipFree(s->d_beams[i]);
+        s->h_beams[i] = nullptr;
+        s->d_beams[i] = nullptr;
     }
-    if (s->d_counters) (void)hipFree(s->d_counters);
     if (s->h_totals) (void)hipHostFree(s->h_totals);
+    s->h_totals = nullptr;
     for (uint8_t* p : s->host_bufs)
         if (p) (void)hipHostFree(p);
+    s->host_bufs.clear();
+    s->host_busy.clear();
+    if (s->rfi_ws) (void)hipFree(s->rfi_ws);
+    if (s->d_mask) (void)hipFree(s->d_mask);
+    s->rfi_ws = nullptr;
+    s->d_mask = nullptr;
+}
+
+void free_server(dedisp_server_s* s) {
+    free_buffers(s);
+    if (s->d_counters) (void)hipFree(s->d_counters);
     if (s->copy_s) (void)hipStreamDestroy(s->copy_s);
     if (s->comp_s) (void)hipStreamDestroy(s->comp_s);
     if (s->done_s) (void)hipStreamDestroy(s->done_s);
     delete s;
+}
+
+// Bytes of one chunk slot: window, workspace, series (and its baseline-
+// removed copy), search workspace, events and candidates.
+size_t slot_bytes(const std::vector<dedisp_plan>& plans, int64_t C, const dd::Widths& W, int R) {
+    int64_t H = 0, ndm = 0, nchans = 0;
+    const int w_max = W.w[W.n - 1];
+    for (const dedisp_plan_s* p : plans) {
+        H = std::max<int64_t>(H, p->max_delay + w_max - 1 + 2 * static_cast<int64_t>(R));
+        ndm = std::max<int64_t>(ndm, p->ndm);
+        nchans = std::max<int64_t>(nchans, p->nchans);
+    }
+    const int64_t win = H + C;
+    const int64_t nser = C + w_max - 1;              // series length the search covers
+    const size_t a = static_cast<size_t>(win * nchans / 4);
+    const size_t b = static_cast<size_t>(nchans) * dd::repack_words(win) * sizeof(uint2);
+    const size_t c = static_cast<size_t>(ndm) * (nser + 2 * static_cast<int64_t>(R)) * 2;
+    const size_t f = R ? static_cast<size_t>(ndm) * nser * 2 : 0;
+    const size_t d = dd::peaks_layout(static_cast<int>(ndm), nser, W).bytes;
+    const size_t e = 2 * static_cast<size_t>(1 << 16) * sizeof(dedisp_event);   // events, candidates
+    return a + b + c + f + d + e;
+}
+
+// Overlaps per beam, then as many chunk slots as the budget holds; the
+// coincidence mask needs one slot per beam (a round at once).
+dedisp_status setup_buffers(dedisp_server_s* s) {
+    const int w_max = s->W.w[s->W.n - 1];
+    const int64_t R = s->bl_radius;
+    s->Hb.clear();
+    s->H = 0;
+    for (int b = 0; b < s->nbeams; ++b) {
+        s->Hb.push_back(s->plans[b]->max_delay + w_max - 1 + 2 * R);
+        s->H = std::max(s->H, s->Hb.back());
+    }
+    if (s->C <= s->H)
+        return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "chunk of %lld samples <= overlap %lld",
+                    static_cast<long long>(s->C), static_cast<long long>(s->H));
+    if ((s->C + s->H + 16384 + w_max) * 4 >= (int64_t(1) << 31))
+        return fail(DEDISP_ERR_UNSUPPORTED, "chunk of %lld samples too long",
+                    static_cast<long long>(s->C));
+    const int nchans = s->nchans;
+    const size_t sb = slot_bytes(s->plans, s->C, s->W, s->bl_radius);
+    size_t resident = 0;
+    for (int b = 0; b < s->nbeams; ++b) resident += static_cast<size_t>(s->Hb[b] * nchans / 4);
+    const int nslots = dedisp_serve_admission(s->budget, resident, sb);
+    if (nslots < 1)
+        return fail(DEDISP_ERR_OUT_OF_MEMORY,
+                    "HBM budget %zu bytes below overlap (%zu) + one chunk slot (%zu)", s->budget,
+                    resident, sb);
+    if (s->rfi_min && nslots < s->nbeams)
+        return fail(DEDISP_ERR_OUT_OF_MEMORY,
+                    "the coincidence mask takes a round of %d chunks at once: the budget holds %d slots",
+                    s->nbeams, nslots);
+    hipError_t e = hipSuccess;
+    const int64_t win = s->H + s->C;
+    const int64_t nser = s->C + w_max - 1;
+    s->overlap.assign(s->nbeams, nullptr);
+    for (int b = 0; b < s->nbeams && e == hipSuccess; ++b)
+        e = hipMalloc(&s->overlap[b], static_cast<size_t>(s->Hb[b] * nchans / 4));
+    s->slots.resize(nslots);
+    size_t wsb = 0;
+    for (const dedisp_plan_s* p : s->plans)
+        wsb = std::max(wsb, static_cast<size_t>(p->nchans) * dd::repack_words(win) * sizeof(uint2));
+    const size_t cl_ws = s->cluster_on ? dd::cluster_workspace_bytes(s->capacity, static_cast<int32_t>(s->ndm_max), s->W.n) : 0;
+    for (int i = 0; i < nslots && e == hipSuccess; ++i) {
+        Slot& sl = s->slots[i];
+        e = hipMalloc(&sl.window, static_cast<size_t>(win * nchans / 4));
+        if (e == hipSuccess) e = hipMalloc(&sl.words, wsb);
+        if (e == hipSuccess) e = hipMalloc(&sl.out, static_cast<size_t>(s->ndm_max) * (nser + 2 * R) * 2);
+        if (e == hipSuccess && R) e = hipMalloc(&sl.flat, static_cast<size_t>(s->ndm_max) * nser * 2);
+        if (e == hipSuccess)
+            e = hipMalloc(&sl.pk_ws, dd::peaks_layout(static_cast<int>(s->ndm_max), nser, s->W).bytes);
+        if (e == hipSuccess) e = hipMalloc(&sl.d_events, static_cast<size_t>(s->capacity) * sizeof(dedisp_event));
+        if (e == hipSuccess) e = hipMalloc(&sl.d_cand, static_cast<size_t>(s->capacity) * sizeof(dedisp_event));
+        if (e == hipSuccess && cl_ws) e = hipMalloc(&sl.cl_ws, cl_ws);
+        if (e == hipSuccess && cl_ws)
+            e = hipMalloc(&sl.d_clusters, static_cast<size_t>(s->capacity) * sizeof(dedisp_cluster));
+    }
+    for (int i = 0; i < dedisp_server_s::kRing && e == hipSuccess; ++i) {
+        e = hipHostMalloc(&s->h_beams[i], sizeof(dd::BeamArgs) * nslots, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc(&s->d_beams[i], sizeof(dd::BeamArgs) * nslots);
+    }
+    if (e == hipSuccess) e = hipHostMalloc(&s->h_totals, sizeof(int64_t) * nslots, hipHostMallocDefault);
+    const int nhost = 2 * nslots + s->nbeams;
+    s->host_bufs.assign(nhost, nullptr);
+    s->host_busy.assign(nhost, false);
+    for (int i = 0; i < nhost && e == hipSuccess; ++i)
+        e = hipHostMalloc(&s->host_bufs[i], static_cast<size_t>(s->C * nchans / 4), hipHostMallocDefault);
+    if (e == hipSuccess && s->rfi_min) {
+        e = hipMalloc(&s->rfi_ws, dd::rfi_mask_ws_bytes(s->nbeams, s->C));
+        if (e == hipSuccess) e = hipMalloc(&s->d_mask, static_cast<size_t>(s->C));
+    }
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? DEDISP_ERR_OUT_OF_MEMORY : DEDISP_ERR_HIP,
+                    "server buffers: %s", hipGetErrorString(e));
+    return DEDISP_OK;
 }
 
 }  // namespace
@@ -422,23 +630,12 @@ extern "C" size_t dedisp_serve_slot_bytes(const dedisp_plan* plans, int32_t nbea
                                           int64_t chunk_nsamps, const int32_t* widths,
                                           int32_t nwidths) {
     if (!plans || nbeams < 1 || chunk_nsamps < 1 || !widths || nwidths < 1) return 0;
-    int64_t H = 0, ndm = 0, nchans = 0;
-    const int w_max = widths[nwidths - 1];
-    for (int b = 0; b < nbeams; ++b) {
+    for (int b = 0; b < nbeams; ++b)
         if (!plans[b]) return 0;
-        H = std::max<int64_t>(H, plans[b]->max_delay + w_max - 1);
-        ndm = std::max<int64_t>(ndm, plans[b]->ndm);
-        nchans = std::max<int64_t>(nchans, plans[b]->nchans);
-    }
-    const int64_t win = H + chunk_nsamps;
     dd::Widths W;
-    if (dd::check_widths_public(widths, nwidths, chunk_nsamps + w_max - 1, &W) != DEDISP_OK) return 0;
-    const size_t a = static_cast<size_t>(win * nchans / 4);
-    const size_t b = static_cast<size_t>(nchans) * dd::repack_words(win) * sizeof(uint2);
-    const size_t c = static_cast<size_t>(ndm) * (chunk_nsamps + w_max - 1) * 2;
-    const size_t d = dd::peaks_layout(static_cast<int>(ndm), chunk_nsamps + w_max - 1, W).bytes;
-    const size_t e = 2 * static_cast<size_t>(1 << 16) * sizeof(dedisp_event);   // events, candidates
-    return a + b + c + d + e;
+    if (dd::check_widths_public(widths, nwidths, chunk_nsamps + widths[nwidths - 1] - 1, &W) != DEDISP_OK)
+        return 0;
+    return slot_bytes(std::vector<dedisp_plan>(plans, plans + nbeams), chunk_nsamps, W, 0);
 }
 
 extern "C" dedisp_status dedisp_serve_create(const dedisp_plan* plans, int32_t nbeams,
@@ -474,21 +671,7 @@ extern "C" dedisp_status dedisp_serve_create(const dedisp_plan* plans, int32_t n
     s->kmant = km;
     s->kexp2 = ke;
     s->model = model;
-    const int w_max = W.w[W.n - 1];
-    for (int b = 0; b < nbeams; ++b) {
-        s->Hb.push_back(plans[b]->max_delay + w_max - 1);
-        s->H = std::max(s->H, s->Hb.back());
-    }
-    if (s->C <= s->H) {
-        delete s;
-        return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "chunk of %lld samples <= overlap %lld",
-                    static_cast<long long>(chunk_nsamps), static_cast<long long>(s->H));
-    }
-    if ((s->C + s->H + 16384 + w_max) * 4 >= (int64_t(1) << 31)) {
-        delete s;
-        return fail(DEDISP_ERR_UNSUPPORTED, "chunk of %lld samples too long",
-                    static_cast<long long>(chunk_nsamps));
-    }
+    s->budget = hbm_budget_bytes;
     s->deadline_ns = static_cast<double>(s->C) * plans[0]->tsamp * 1e9;
     s->nl = dd::levels_for(nchans);
     s->cfg = dd::default_tile_config(plans[0]);
@@ -505,47 +688,16 @@ extern "C" dedisp_status dedisp_serve_create(const dedisp_plan* plans, int32_t n
             return st;
         }
     }
-    // HBM admission: resident overlaps first, then as many chunk slots as fit.
-    const size_t slot_bytes = dedisp_serve_slot_bytes(plans, nbeams, chunk_nsamps, widths, nwidths);
-    size_t resident = 0;
-    for (int b = 0; b < nbeams; ++b) resident += static_cast<size_t>(s->Hb[b] * nchans / 4);
-    const int nslots = dedisp_serve_admission(hbm_budget_bytes, resident, slot_bytes);
-    if (nslots < 1) {
-        delete s;
-        return fail(DEDISP_ERR_OUT_OF_MEMORY,
-                    "HBM budget %zu bytes below overlap (%zu) + one chunk slot (%zu)",
-                    hbm_budget_bytes, resident, slot_bytes);
-    }
-    hipError_t e = hipSuccess;
-    const int64_t win = s->H + s->C;
     int64_t ndm_max = 0;
     for (int b = 0; b < nbeams; ++b) ndm_max = std::max<int64_t>(ndm_max, plans[b]->ndm);
     s->ndm_max = ndm_max;
-    s->overlap.assign(nbeams, nullptr);
-    for (int b = 0; b < nbeams && e == hipSuccess; ++b)
-        e = hipMalloc(&s->overlap[b], static_cast<size_t>(s->Hb[b] * nchans / 4));
-    s->slots.resize(nslots);
-    for (int i = 0; i < nslots && e == hipSuccess; ++i) {
-        Slot& sl = s->slots[i];
-        e = hipMalloc(&sl.window, static_cast<size_t>(win * nchans / 4));
-        if (e == hipSuccess) e = hipMalloc(&sl.words, static_cast<size_t>(nchans) * dd::repack_words(win) * sizeof(uint2));
-        if (e == hipSuccess) e = hipMalloc(&sl.out, static_cast<size_t>(ndm_max) * (s->C + w_max - 1) * 2);
-        if (e == hipSuccess)
-            e = hipMalloc(&sl.pk_ws, dd::peaks_layout(static_cast<int>(ndm_max), s->C + w_max - 1, W).bytes);
-        if (e == hipSuccess) e = hipMalloc(&sl.d_events, static_cast<size_t>(s->capacity) * sizeof(dedisp_event));
-        if (e == hipSuccess) e = hipMalloc(&sl.d_cand, static_cast<size_t>(s->capacity) * sizeof(dedisp_event));
+    // HBM admission: resident overlaps first, then as many chunk slots as fit.
+    st = setup_buffers(s);
+    if (st != DEDISP_OK) {
+        free_server(s);
+        return st;
     }
-    for (int i = 0; i < dedisp_server_s::kRing && e == hipSuccess; ++i) {
-        e = hipHostMalloc(&s->h_beams[i], sizeof(dd::BeamArgs) * nslots, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipMalloc(&s->d_beams[i], sizeof(dd::BeamArgs) * nslots);
-    }
-    if (e == hipSuccess) e = hipMalloc(&s->d_counters, sizeof(unsigned long long) * s->nq);
-    if (e == hipSuccess) e = hipHostMalloc(&s->h_totals, sizeof(int64_t) * nslots, hipHostMallocDefault);
-    const int nhost = 2 * nslots + nbeams;
-    s->host_bufs.assign(nhost, nullptr);
-    s->host_busy.assign(nhost, false);
-    for (int i = 0; i < nhost && e == hipSuccess; ++i)
-        e = hipHostMalloc(&s->host_bufs[i], static_cast<size_t>(s->C * nchans / 4), hipHostMallocDefault);
+    hipError_t e = hipMalloc(&s->d_counters, sizeof(unsigned long long) * s->nq);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy_s, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->comp_s, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->done_s, hipStreamNonBlocking);
@@ -585,6 +737,7 @@ extern "C" dedisp_status dedisp_serve_submit(dedisp_server s, int32_t beam, int6
         s->host_busy[hb] = true;
         if (expect >= 0 && seq > expect) flags |= DEDISP_CHUNK_GAP;
         s->next_seq[beam] = seq + 1;
+        s->submitting++;
     }
     std::memcpy(s->host_bufs[hb], host_chunk, static_cast<size_t>(s->C * s->nchans / 4));
     Job j;
@@ -596,6 +749,7 @@ extern "C" dedisp_status dedisp_serve_submit(dedisp_server s, int32_t beam, int6
     {
         std::lock_guard<std::mutex> g(s->mu);
         s->pending.push_back(j);
+        s->submitting--;
     }
     s->cv_sched.notify_one();
     dd::clear_error();
@@ -683,11 +837,60 @@ extern "C" dedisp_status dedisp_serve_set_clustering(dedisp_server s, int32_t dm
     return DEDISP_OK;
 }
 
+extern "C" dedisp_status dedisp_serve_set_stages(dedisp_server s, float rfi_k_sigma,
+                                                 int32_t rfi_min_beams, int32_t baseline_radius) {
+    if (!s) return fail(DEDISP_ERR_INVALID_ARG, "server is NULL");
+    uint32_t km = 0;
+    int ke = 0;
+    if (rfi_k_sigma != 0.0f) {
+        const dedisp_status st = dd::split_threshold_public(rfi_k_sigma, &km, &ke);
+        if (st != DEDISP_OK) return st;
+        if (rfi_min_beams < 1 || rfi_min_beams > s->nbeams || s->nbeams > 64)
+            return fail(DEDISP_ERR_INVALID_ARG, "min_beams %d outside [1, %d] (at most 64 beams)",
+                        rfi_min_beams, s->nbeams);
+    }
+    if (baseline_radius < 0 || baseline_radius > 8192)
+        return fail(DEDISP_ERR_INVALID_ARG, "baseline radius %d outside [0, 8192]", baseline_radius);
+    if (baseline_radius > 0 && 6 * s->nchans > 65535)
+        return fail(DEDISP_ERR_UNSUPPORTED, "uint16 baseline output needs 6 nchans <= 65535");
+    std::lock_guard<std::mutex> g(s->mu);
+    for (int64_t q : s->next_seq)
+        if (q >= 0) return fail(DEDISP_ERR_BUSY, "stages must be set before the first submit");
+    // nothing is in flight: size the buffers for the new stages
+    const int old_r = s->bl_radius, old_m = s->rfi_min;
+    const uint32_t old_km = s->rfi_kmant;
+    const int old_ke = s->rfi_kexp2;
+    free_buffers(s);
+    s->bl_radius = baseline_radius;
+    s->rfi_min = rfi_k_sigma != 0.0f ? rfi_min_beams : 0;
+    s->rfi_kmant = km;
+    s->rfi_kexp2 = ke;
+    dedisp_status st = setup_buffers(s);
+    if (st != DEDISP_OK) {
+        const std::string msg = dedisp_last_error();
+        free_buffers(s);
+        s->bl_radius = old_r;
+        s->rfi_min = old_m;
+        s->rfi_kmant = old_km;
+        s->rfi_kexp2 = old_ke;
+        if (setup_buffers(s) != DEDISP_OK) {
+            s->async_error = DEDISP_ERR_OUT_OF_MEMORY;
+            s->async_msg = "server buffers could not be restored";
+        }
+        return fail(st, "%s", msg.c_str());
+    }
+    dd::clear_error();
+    return DEDISP_OK;
+}
+
 extern "C" dedisp_status dedisp_serve_destroy(dedisp_server s) {
     if (!s) return fail(DEDISP_ERR_INVALID_ARG, "server is NULL");
     {
-        // let queued work finish before stopping
+        // let queued work finish before stopping (rounds of the coincidence
+        // mask that some beam never completed go as they are)
         std::unique_lock<std::mutex> lk(s->mu);
+        s->draining = true;
+        s->cv_sched.notify_all();
         s->cv_poll.wait_for(lk, std::chrono::seconds(600), [&] {
             return s->async_error != DEDISP_OK || (s->pending.empty() && s->inflight.empty() && s->ring_used == 0);
         });

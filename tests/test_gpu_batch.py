@@ -205,3 +205,86 @@ def test_batch_at_multibeam_survey_shape():
                 mine = [e for e in b_ev if int(e["width_idx"]) == wi and int(e["dm_idx"]) == d]
                 events_equal(mine, want)
         log("beam", b, "n", n, "events", counts[b], "rows", rows, "ok")
+
+
+def test_batch_stages_equal_standalone_and_oracle_chain():
+    """The batch with its optional stages -- coincidence mask before
+    dedispersion, baseline removal after -- gives every beam the events of
+    the standalone chain (dedisp_rfi_mask + dedisp_rfi_apply on copies of the
+    inputs over the samples all beams share, dedisp_execute, baseline_remove,
+    find_peaks) bit for bit, and two beams the events of the oracle chain;
+    the graph is captured again when the stages change, and switching them
+    off restores the plain results."""
+    from paper_1112_0065_amd import _lib as L
+    torch = torch_dev()
+    nb, nch, n0, R, K, MB = 6, 256, 30000, 48, 3.0, 3
+    packed, imps, _, _ = synth.make_coincidence_beams(31, nbeams=nb, nsamps=n0, nchans=nch,
+                                                      npulses=2, impulse_rate=40.0, dm_max=150.0)
+    bpc = nch // 4
+    ns = [n0 - 1500 * b for b in range(nb)]                 # uneven lengths
+    n_common = min(ns)
+    dms = [synth.dm_list_linear(48, 60.0 + 20.0 * b) for b in range(nb)]
+    plans = [L.dedisp_plan_create(nch, synth.F_TOP, -400.0 / nch, synth.TSAMP, dms[b])
+             for b in range(nb)]
+    ins = [to_dev(packed[b][:ns[b] * bpc].copy()) for b in range(nb)]
+    outs = [torch.empty((48, ns[b] - plans[b].max_delay), dtype=torch.int16, device="cuda")
+            for b in range(nb)]
+    evs = [torch.empty(4096 * 40, dtype=torch.uint8, device="cuda") for _ in range(nb)]
+    caps = [4096] * nb
+    batch = L.dedisp_batch_create(plans, WIDTHS, 5.0, out_u16=True)
+    plain = L.dedisp_batch_execute(batch, ins, ns, outs, evs, caps)
+    plain_ev = [L.events_from_buffer(evs[b], plain[b]).tobytes() for b in range(nb)]
+    L.dedisp_batch_set_stages(batch, K, MB, R)
+    counts = L.dedisp_batch_execute(batch, ins, ns, outs, evs, caps)
+    got = [L.events_from_buffer(evs[b], counts[b]) for b in range(nb)]
+    # the inputs are untouched
+    for b in range(nb):
+        assert (ins[b].cpu().numpy() == packed[b][:ns[b] * bpc]).all()
+
+    # standalone chain
+    ws = torch.empty(L.dedisp_rfi_mask_workspace_bytes(nb, n_common), dtype=torch.uint8,
+                     device="cuda")
+    mask = torch.empty(n_common, dtype=torch.uint8, device="cuda")
+    nmask = L.dedisp_rfi_mask(ins, nch, n_common, K, MB, mask, ws)
+    log("batch stages: flagged samples", nmask, "impulses", len(imps))
+    assert nmask > 0
+    copies = [t.clone() for t in ins]
+    L.dedisp_rfi_apply(copies, nch, n_common, mask)
+    for b in range(nb):
+        p = plans[b]
+        nout = ns[b] - p.max_delay
+        out = torch.empty((48, nout), dtype=torch.int16, device="cuda")
+        dws = torch.empty(L.dedisp_workspace_bytes(p, ns[b]), dtype=torch.uint8, device="cuda")
+        L.dedisp_execute(p, copies[b], ns[b], out, dws)
+        flat = torch.empty((48, nout - 2 * R), dtype=torch.int16, device="cuda")
+        L.baseline_remove(out, 48, nout, R, 3 * nch, flat)
+        pws = torch.empty(L.find_peaks_workspace_bytes(48, nout - 2 * R, WIDTHS),
+                          dtype=torch.uint8, device="cuda")
+        evb = torch.empty(4096 * 40, dtype=torch.uint8, device="cuda")
+        n = L.find_peaks(flat, 48, nout - 2 * R, WIDTHS, 5.0, evb, 4096, pws)
+        ref = L.events_from_buffer(evb, n)
+        assert n == counts[b] and ref.tobytes() == got[b].tobytes(), b
+        assert (out.cpu().numpy() == outs[b].cpu().numpy()).all()
+
+    # oracle chain on two beams
+    zs = [oracle.zero_dm_series(packed[b][:n_common * bpc], n_common, nch) for b in range(nb)]
+    omask, _, _ = oracle.rfi_mask(zs, K, MB)
+    assert (omask == mask.cpu().numpy().astype(bool)).all()
+    for b in (0, nb - 1):
+        p = plans[b]
+        x = oracle.unpack_2bit(packed[b][:ns[b] * bpc], ns[b], nch)
+        full_mask = np.zeros(ns[b], bool)
+        full_mask[:n_common] = omask
+        x = oracle.replace_masked(x, full_mask)
+        dly = oracle.delay_table(nch, synth.F_TOP, -400.0 / nch, synth.TSAMP, dms[b])
+        ded = oracle.dedisperse(x, dly)
+        flat = oracle.baseline_remove(ded, R, 3 * nch)
+        events_equal(got[b], oracle.find_events(oracle.boxcar(flat, WIDTHS), 5.0))
+
+    # stages off: the plain results again, from a fresh capture
+    L.dedisp_batch_set_stages(batch, 0.0, 0, 0)
+    again = L.dedisp_batch_execute(batch, ins, ns, outs, evs, caps)
+    assert again == plain
+    assert [L.events_from_buffer(evs[b], again[b]).tobytes() for b in range(nb)] == plain_ev
+    _, _, captures = L.dedisp_batch_info(batch)
+    assert captures == 3

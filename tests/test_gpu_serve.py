@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_common import events_equal, log, torch_dev
+from gpu_common import events_equal, log, to_dev, torch_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -256,3 +256,79 @@ def test_serve_clusters_each_chunk():
     log(f"served {total_ev} events in {total_cl} clusters")
     assert total_ev > total_cl > 0
     srv.close()
+
+
+def test_serve_stages_equal_standalone_chain():
+    """With the coincidence mask (per round of chunks) and baseline removal
+    on, every served chunk equals the standalone chain on its window: the
+    round's mask (dedisp_rfi_mask over the round's raw chunks) applied to
+    each chunk, the window of the masked stream (overlap grown by 2R),
+    dedisp_execute, baseline_remove, find_peaks; one window also equals the
+    oracle chain.  A round runs as one batch."""
+    from paper_1112_0065_amd import _lib as L
+    torch = torch_dev()
+    nb, nch, nk, R, KR, MB = 4, NCH, 3, 32, 3.0, 2
+    packed, imps, _, _ = synth.make_coincidence_beams(41, nbeams=nb, nsamps=nk * C, nchans=nch,
+                                                      npulses=3, impulse_rate=30.0, dm_max=100.0)
+    bpc = nch // 4
+    dms = [synth.dm_list_linear(64, 60.0 + 10.0 * b) for b in range(nb)]
+    plans = [L.dedisp_plan_create(nch, synth.F_TOP, -400.0 / nch, synth.TSAMP, dms[b])
+             for b in range(nb)]
+    budget = 30 * L.dedisp_serve_slot_bytes(plans, C, WIDTHS)
+    srv = L.dedisp_serve_create(plans, C, WIDTHS, K, budget)
+    L.dedisp_serve_set_stages(srv, KR, MB, R)
+    for k in range(nk):
+        for b in range(nb):
+            while not L.dedisp_serve_submit(srv, b, k, packed[b][k * C * bpc:(k + 1) * C * bpc],
+                                            L.dedisp_now_ns()):
+                time.sleep(0.01)
+    res = _drain(srv, nb * nk)
+    st = L.dedisp_serve_stats(srv)
+    with pytest.raises(L.DedispError) as ei:
+        L.dedisp_serve_set_stages(srv, 0.0, 0, 0)
+    assert ei.value.status == L.ERR_BUSY
+    srv.close()
+    log("serve stages stats", st)
+    assert st["max_batch"] >= nb
+
+    # the masked streams, round by round
+    masked = [np.empty(nk * C * bpc, np.uint8) for _ in range(nb)]
+    ws = torch.empty(L.dedisp_rfi_mask_workspace_bytes(nb, C), dtype=torch.uint8, device="cuda")
+    mask = torch.empty(C, dtype=torch.uint8, device="cuda")
+    flagged = 0
+    for k in range(nk):
+        chunks = [to_dev(packed[b][k * C * bpc:(k + 1) * C * bpc].copy()) for b in range(nb)]
+        flagged += L.dedisp_rfi_mask(chunks, nch, C, KR, MB, mask, ws)
+        L.dedisp_rfi_apply(chunks, nch, C, mask)
+        for b in range(nb):
+            masked[b][k * C * bpc:(k + 1) * C * bpc] = chunks[b].cpu().numpy()
+    log("flagged samples", flagged, "impulses", len(imps))
+    assert flagged > 0
+    checked_oracle = False
+    for r in res:
+        b, k = r["beam"], r["seq"]
+        p = plans[b]
+        Hb = p.max_delay + WIDTHS[-1] - 1 + 2 * R
+        start = 0 if k == 0 else k * C - Hb
+        nsamps = (k + 1) * C - start
+        assert r["t_abs0"] == start + R
+        win = masked[b][start * bpc:(k + 1) * C * bpc]
+        nout = nsamps - p.max_delay
+        out = torch.empty((64, nout), dtype=torch.int16, device="cuda")
+        dws = torch.empty(L.dedisp_workspace_bytes(p, nsamps), dtype=torch.uint8, device="cuda")
+        L.dedisp_execute(p, to_dev(win.copy()), nsamps, out, dws)
+        flat = torch.empty((64, nout - 2 * R), dtype=torch.int16, device="cuda")
+        L.baseline_remove(out, 64, nout, R, 3 * nch, flat)
+        pws = torch.empty(L.find_peaks_workspace_bytes(64, nout - 2 * R, WIDTHS), dtype=torch.uint8,
+                          device="cuda")
+        evb = torch.empty(4096 * 40, dtype=torch.uint8, device="cuda")
+        n = L.find_peaks(flat, 64, nout - 2 * R, WIDTHS, K, evb, 4096, pws)
+        assert n == r["n_events"] and r["n_bx"] == nout - 2 * R - WIDTHS[-1] + 1
+        assert L.events_from_buffer(evb, n).tobytes() == r["events"].tobytes(), (b, k)
+        if k == 1 and not checked_oracle:
+            x = oracle.unpack_2bit(win, nsamps, nch)
+            dly = oracle.delay_table(nch, synth.F_TOP, -400.0 / nch, synth.TSAMP, dms[b])
+            fl = oracle.baseline_remove(oracle.dedisperse(x, dly), R, 3 * nch)
+            events_equal(r["events"], oracle.find_events(oracle.boxcar(fl, WIDTHS), K))
+            checked_oracle = True
+    assert checked_oracle
