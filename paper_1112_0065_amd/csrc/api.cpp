@@ -129,7 +129,7 @@ namespace {
 
 // (dms_per_block, groups) pairs with compiled kernels, times the stage sizes.
 const int kShapes[][2] = {{4, 1}, {8, 1}, {16, 1}, {32, 1}, {4, 2}, {8, 2}, {16, 2}};
-const int kStages[] = {16, 32, 64};
+const int kStages[] = {8, 16, 32};
 
 }  // namespace
 

@@ -49,7 +49,7 @@ struct BeamArgs {
     void* out;               // [ndm][nout]
     int n_dm_blocks;
     int tile_words;          // T/32 + 1 of the launch's tile shape
-    int pitch;               // words per LDS row: tile_words + the largest block skew
+    int pitch;               // 16-byte quads per LDS row: tile_words - 1 + the largest block skew
     int dm_group;            // DM blocks per group of the work-item order
     int64_t item_begin;      // first work item of this beam in a batch
     int64_t n_items;         // time tiles x DM blocks
@@ -112,11 +112,12 @@ BeamArgs beam_args(const dedisp_plan_s* p, const uint2* words, int64_t nwords, i
 size_t tile_lds_bytes(const dedisp_plan_s* p, const TileConfig& cfg);
 int tile_pitch(const dedisp_plan_s* p, const TileConfig& cfg);
 // Device table of the tile shape, [ndm][nchans] entries
-//     ((c mod CS) * pitch + (delay[d][c] >> 5) - (delay[d_lo][c] >> 5)) * 8 << 5
+//     ((c mod CS) * pitch + (delay[d][c] >> 5) - (delay[d_lo][c] >> 5)) * 16 << 5
 //   | (delay[d][c] & 31)
-// with d_lo the block's first trial and pitch = 64*G + 1 + (largest block
-// skew): the byte offset, in an LDS stage buffer, of the first word the trial
-// reads of channel c, and the shift within it.  Built (synchronously: hipMalloc + hipMemcpy) on first use of the
+// with d_lo the block's first trial and pitch = 64*G + (largest block skew)
+// quads per row: the byte offset, in an LDS stage buffer, of the quad (the
+// 16-byte copy of two consecutive words) the trial reads first for channel
+// c, and the shift within it.  Built (synchronously: hipMalloc + hipMemcpy) on first use of the
 // shape; `build` false only looks it up.  Returns nullptr on failure.
 const uint32_t* offset_table(const dedisp_plan_s* p, const TileConfig& cfg, bool build,
                              dedisp_status* st = nullptr);

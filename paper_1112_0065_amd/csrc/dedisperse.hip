@@ -9,10 +9,13 @@
 //     32-sample groups (lane-strided, so LDS reads are conflict-free);
 //   * channels are streamed in stages of CS channels: the block copies, per
 //     channel, the skewed window of words all its trials need into LDS
-//     (one coalesced load shared by the ND trials);
-//   * per (trial, channel) a lane reads two words per group at an LDS offset
-//     taken from the plan's per-tile-shape offset table (one scalar load per
-//     channel; the table also carries the shift within the word), aligns them
+//     (one coalesced load shared by the ND trials), as 16-byte quads that
+//     each hold two consecutive words (every word is stored twice);
+//   * per (trial, channel) a lane reads one aligned quad per group (one
+//     ds_read_b128, which moves about 1.5x the bytes per clock of the two
+//     8-byte reads of unaligned word pairs) at an LDS offset taken from the
+//     plan's per-tile-shape offset table (one scalar load per channel; the
+//     table also carries the shift within the word), aligns the two words
 //     to the trial's delay with one funnel shift per plane, and adds the 32
 //     2-bit samples into a bit-sliced counter with carry-save adder trees:
 //     about 8 bit-operations add 32 samples (see gen_csa.py);
@@ -75,10 +78,12 @@ DD_CSA_SPEC(16, 4) DD_CSA_SPEC(16, 8) DD_CSA_SPEC(16, 16) DD_CSA_SPEC(16, 32)
 // Accumulate channels [c, c+N) of the current stage for one trial into the
 // counters of its G groups.
 // The trial's offset-table row gives, per channel, the LDS byte offset of the
-// channel's first needed word (bits 5 and up) and the funnel shift (bits 0-4,
-// which is all the shift instruction reads).
+// channel's first needed quad (bits 5 and up) and the funnel shift (bits 0-4,
+// which is all the shift instruction reads).  A quad is a 16-byte aligned
+// copy of two consecutive words, so each (trial, channel, group) is one
+// aligned 16-byte LDS read.
 template <int NL, int G, int N>
-__device__ __forceinline__ void accumulate_chunk(uint32_t (&acc)[G][NL], const uint2* lds_lane,
+__device__ __forceinline__ void accumulate_chunk(uint32_t (&acc)[G][NL], const char* lds_lane,
                                                  cptr<uint32_t> trow, int c) {
     uint32_t e[N];
 #pragma unroll
@@ -88,13 +93,8 @@ __device__ __forceinline__ void accumulate_chunk(uint32_t (&acc)[G][NL], const u
         // all N reads first, then the shifts: the reads' latencies overlap
         uint4 w[N];
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-            const uint2* p = reinterpret_cast<const uint2*>(
-                                 reinterpret_cast<const char*>(lds_lane) + (e[k] >> 5)) + 64 * g;
-            const uint2 w0 = p[0];
-            const uint2 w1 = p[1];
-            w[k] = make_uint4(w0.x, w0.y, w1.x, w1.y);
-        }
+        for (int k = 0; k < N; ++k)
+            w[k] = *reinterpret_cast<const uint4*>(lds_lane + (e[k] >> 5) + 1024 * g);
         uint32_t lo[N], hi[N];
 #pragma unroll
         for (int k = 0; k < N; ++k) {
@@ -106,28 +106,29 @@ __device__ __forceinline__ void accumulate_chunk(uint32_t (&acc)[G][NL], const u
 }
 
 // Asynchronous copy of one LDS stage: channels [c0, c0 + cs) of the block's
-// window, channel cl into row `row0 + cl` (pitch `a.pitch` words).  Each row
-// gets the `stride` words from w_base + (delay[d_lo][c] >> 5) on, cut at the
-// end of the channel's words (what lies beyond only feeds output samples past
-// nout, which are never stored).  The copies go global -> LDS directly (one
-// dword per lane and instruction) and complete asynchronously: the caller
-// waits for them before the barrier that publishes the stage.
+// window, channel cl into row `cl` (a.pitch quads of 16 bytes).  Quad j of a
+// row holds the words j and j + 1 of the window that starts at word
+// w_base + (delay[d_lo][c] >> 5): stride - 1 quads cover the `stride` words,
+// cut at the end of the channel's words (what lies beyond only feeds output
+// samples past nout, which are never stored).  Each lane copies one quad,
+// global -> LDS directly (16 bytes from an 8-byte aligned word address); the
+// copies complete asynchronously: the caller waits for them before the
+// barrier that publishes the stage.
 __device__ __forceinline__ void fill_stage(const dd::BeamArgs& a, cptr<int32_t> dlo_row,
                                            int64_t w_base, int stride, int c0, int cs,
-                                           uint2* __restrict__ lds, int lane, int wave) {
+                                           char* __restrict__ lds, int lane, int wave) {
     for (int cl = wave; cl < cs; cl += kWaves) {
         const int c = c0 + cl;
         const int64_t w0 = w_base + (dlo_row[c] >> 5);
         const int64_t avail = a.nwords - w0;   // > 0: w0 < nsamps / 32 + 1 < nwords
-        const int ndw = 2 * static_cast<int>(avail < stride ? avail : stride);
-        const uint32_t* src =
-            reinterpret_cast<const uint32_t*>(a.words + static_cast<int64_t>(c) * a.nwords + w0);
-        uint32_t* dst = reinterpret_cast<uint32_t*>(lds + static_cast<int64_t>(cl) * a.pitch);
-        for (int i = 0; i < ndw; i += 64) {
-            if (i + lane < ndw)
+        const int nq = static_cast<int>((avail < stride ? avail : stride) - 1);
+        const uint2* src = a.words + static_cast<int64_t>(c) * a.nwords + w0;
+        char* dst = lds + static_cast<int64_t>(cl) * a.pitch * 16;
+        for (int i = 0; i < nq; i += 64) {
+            if (i + lane < nq)
                 __builtin_amdgcn_global_load_lds(
                     (const __attribute__((address_space(1))) void*)(src + i + lane),
-                    (__attribute__((address_space(3))) void*)(dst + i), 4, 0, 0);
+                    (__attribute__((address_space(3))) void*)(dst + 16 * i), 16, 0, 0);
         }
     }
 }
@@ -139,7 +140,7 @@ template <int NL, int NDW, int G>
 __device__ __forceinline__ void run_stage(const dd::BeamArgs& a, uint32_t (&acc)[NDW][G][NL],
                                           cptr<int32_t> dlo_row, int64_t w_base, int stride,
                                           int c0, int stage_chans, int d_lo,
-                                          const uint2* __restrict__ cur, uint2* __restrict__ nxt,
+                                          const char* __restrict__ cur, char* __restrict__ nxt,
                                           bool more, int lane, int wave) {
     const int cs = min(stage_chans, a.nchans - c0);
     if (more)
@@ -154,8 +155,8 @@ __device__ __forceinline__ void run_stage(const dd::BeamArgs& a, uint32_t (&acc)
             // 8-channel steps: fewer live registers than 16, more resident waves
 #pragma unroll 1
             for (; cl + 8 <= cs; cl += 8)
-                accumulate_chunk<NL, G, 8>(acc[i], cur + lane, trow, c0 + cl);
-            if (cl + 4 <= cs) accumulate_chunk<NL, G, 4>(acc[i], cur + lane, trow, c0 + cl);
+                accumulate_chunk<NL, G, 8>(acc[i], cur + 16 * lane, trow, c0 + cl);
+            if (cl + 4 <= cs) accumulate_chunk<NL, G, 4>(acc[i], cur + 16 * lane, trow, c0 + cl);
         }
     }
 }
@@ -168,12 +169,12 @@ __device__ __forceinline__ void run_stage(const dd::BeamArgs& a, uint32_t (&acc)
 // stage s + 1 into the other buffer is in flight.
 template <int NL, int NDW, int G, bool OUT16>
 __device__ __forceinline__ void process_item(const dd::BeamArgs& a, int tile, int dblk,
-                                             int stage_chans, uint2* lds, int lane, int wave) {
+                                             int stage_chans, char* lds, int lane, int wave) {
     constexpr int ND = NDW * kWaves;
     constexpr int T = 2048 * G;
     const int64_t T0 = static_cast<int64_t>(tile) * T;
     const int d_lo = dblk * ND;
-    // words this block needs per channel row (<= a.pitch)
+    // words this block needs per channel row (<= a.pitch + 1)
     const int stride = a.tile_words + as_const(a.skew)[dblk];
     const int64_t w_base = T0 >> 5;
     const cptr<int32_t> dlo_row = as_const(a.delays) + static_cast<int64_t>(d_lo) * a.nchans;
@@ -188,7 +189,7 @@ __device__ __forceinline__ void process_item(const dd::BeamArgs& a, int tile, in
             for (int l = 0; l < NL; ++l) acc[i][g][l] = 0u;
 
     fill_stage(a, dlo_row, w_base, stride, 0, min(stage_chans, a.nchans), lds, lane, wave);
-    const int64_t half = static_cast<int64_t>(stage_chans) * a.pitch;
+    const int64_t half = static_cast<int64_t>(stage_chans) * a.pitch * 16;   // bytes
 #pragma unroll 1
     for (int st = 0; st < nst; ++st) {
         const int c0 = st * stage_chans;
@@ -271,7 +272,7 @@ __device__ __forceinline__ void item_coords(const dd::BeamArgs& a, int64_t item,
 template <int NL, int NDW, int G, bool OUT16>
 __global__ __launch_bounds__(kThreads) void dedisperse_kernel(dd::BeamArgs a, int stage_chans,
                                                               int n_items) {
-    extern __shared__ uint2 lds[];
+    extern __shared__ uint4 lds[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // XCD-aware order: hardware deals consecutive blocks round-robin to the 8
@@ -283,7 +284,8 @@ __global__ __launch_bounds__(kThreads) void dedisperse_kernel(dd::BeamArgs a, in
     if (item >= n_items) return;
     int tile, dblk;
     item_coords(a, item, &tile, &dblk);
-    process_item<NL, NDW, G, OUT16>(a, tile, dblk, stage_chans, lds, lane, wave);
+    process_item<NL, NDW, G, OUT16>(a, tile, dblk, stage_chans, reinterpret_cast<char*>(lds), lane,
+                                    wave);
 }
 
 // Persistent form over the work items of several beams: blocks pop items
@@ -295,7 +297,7 @@ template <int NL, int NDW, int G, bool OUT16>
 __global__ __launch_bounds__(kThreads) void dedisperse_persistent_kernel(
     const dd::BeamArgs* __restrict__ beams, int nbeams, int64_t total, int stage_chans,
     unsigned long long* __restrict__ counters, int nq) {
-    extern __shared__ uint2 lds[];
+    extern __shared__ uint4 lds[];
     __shared__ long long item_sh;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -320,7 +322,8 @@ __global__ __launch_bounds__(kThreads) void dedisperse_persistent_kernel(
         const int64_t local = item - a.item_begin;
         int tile, dblk;
         item_coords(a, local, &tile, &dblk);
-        process_item<NL, NDW, G, OUT16>(a, tile, dblk, stage_chans, lds, lane, wave);
+        process_item<NL, NDW, G, OUT16>(a, tile, dblk, stage_chans, reinterpret_cast<char*>(lds),
+                                        lane, wave);
     }
 }
 
@@ -379,13 +382,14 @@ namespace dd {
 
 
 int tile_pitch(const dedisp_plan_s* p, const TileConfig& cfg) {
+    // quads per LDS row: one fewer than the words a row covers
     const int k = dm_block_index(cfg.dms_per_block);
-    return k < 0 ? 0 : 2048 * cfg.groups / 32 + 1 + p->skew_max[k];
+    return k < 0 ? 0 : 2048 * cfg.groups / 32 + p->skew_max[k];
 }
 
 size_t tile_lds_bytes(const dedisp_plan_s* p, const TileConfig& cfg) {
-    // two stage buffers of stage_chans rows
-    return 2 * static_cast<size_t>(cfg.stage_chans) * tile_pitch(p, cfg) * sizeof(uint2);
+    // two stage buffers of stage_chans rows of 16-byte quads
+    return 2 * static_cast<size_t>(cfg.stage_chans) * tile_pitch(p, cfg) * sizeof(uint4);
 }
 
 BeamArgs beam_args(const dedisp_plan_s* p, const uint2* words, int64_t nwords, int64_t nout,

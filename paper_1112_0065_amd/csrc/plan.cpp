@@ -169,16 +169,17 @@ const uint32_t* offset_table(const dedisp_plan_s* p, const TileConfig& cfg, bool
         return nullptr;
     }
     const int nc = p->nchans;
-    const int64_t pitch = 64 * cfg.groups + 1 + p->skew_max[k];
+    // quads (16-byte copies of two consecutive words) per LDS row
+    const int64_t pitch = 64 * cfg.groups + p->skew_max[k];
     std::vector<uint32_t> h(static_cast<size_t>(p->ndm) * nc);
     for (int d = 0; d < p->ndm; ++d) {
         const int blk = d / cfg.dms_per_block;
         const int32_t* row = &p->delays[static_cast<size_t>(d) * nc];
         const int32_t* lo = &p->delays[static_cast<size_t>(blk) * cfg.dms_per_block * nc];
         for (int c = 0; c < nc; ++c) {
-            const int64_t words = (c % cfg.stage_chans) * pitch + (row[c] >> 5) - (lo[c] >> 5);
-            const int64_t bytes = words * 8;
-            if (words < 0 || (bytes << 5) >= (int64_t(1) << 32)) {
+            const int64_t quads = (c % cfg.stage_chans) * pitch + (row[c] >> 5) - (lo[c] >> 5);
+            const int64_t bytes = quads * 16;
+            if (quads < 0 || (bytes << 5) >= (int64_t(1) << 32)) {
                 if (st) *st = fail(DEDISP_ERR_UNSUPPORTED, "LDS offset out of range");
                 return nullptr;
             }

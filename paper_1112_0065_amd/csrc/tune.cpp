@@ -121,7 +121,7 @@ namespace dd {
 TileConfig default_tile_config(const dedisp_plan_s* p) {
     const int packed = p->tuned.load();
     if (packed) return TileConfig{packed >> 16, (packed >> 8) & 0xFF, packed & 0xFF};
-    return TileConfig{16, 1, 16};
+    return TileConfig{16, 1, 8};
 }
 
 TileConfig tuned_or_default(const dedisp_plan_s* p, const char* cache_path, int out_u16) {
@@ -197,7 +197,7 @@ extern "C" dedisp_status dedisp_autotune(dedisp_plan p, int64_t nsamps, dedisp_o
     hipLaunchKernelGGL(fill_random_kernel, dim3(static_cast<unsigned>((in_bytes + 255) / 256)), dim3(256),
                        0, s, in, in_bytes, 0x5EEDull + static_cast<uint64_t>(p->ndm));
     e = dd::launch_repack(in, nsamps, p->nchans, words, nwords, s);
-    const dd::TileConfig base{16, 1, 16};
+    const dd::TileConfig base = dd::default_tile_config(p);
     if (e == hipSuccess)
         st = dd::launch_dedisperse(p, words, nwords, nout, ref, u16, base, s);
     if (e != hipSuccess || st != DEDISP_OK) {
