@@ -54,6 +54,8 @@ HBM_PEAK = 8e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dedisperse_survey_traffic.json")
 KERNEL_SOURCES = ["dedisperse.hip", "bitslice.hpp", "csa_tree.inc", "dedisp_internal.hpp"]
 CHUNK = 1 << 17            # streaming chunk: 8.388608 s at 64 us
+RFI_K, RFI_MIN_BEAMS = 3.0, 4   # coincidence mask: 3 sigma in >= 4 of the 13 beams
+BASELINE_R = 2048               # baseline removal radius (samples)
 T_START = time.perf_counter()
 
 
@@ -222,6 +224,8 @@ def main():
                     help="chunks per beam in the unpaced streaming run")
     ap.add_argument("--serve-speed", type=float, default=1.0,
                     help="arrival rate as a multiple of real time")
+    ap.add_argument("--serve-rfi", type=int, default=1,
+                    help="1: the paced streaming run applies the coincidence mask per round")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--time-budget", type=float, default=540.0,
@@ -362,6 +366,9 @@ def main():
                                         15, lambda: bench_serve_queueing(args, payloads))
             rec["serve_unpaced"] = leg("13-beam streaming, unpaced", 20,
                                        lambda: bench_serve_unpaced(args, payloads))
+            rec["serve_unpaced_stages"] = leg(
+                "13-beam streaming, unpaced, coincidence mask and baseline removal", 20,
+                lambda: bench_serve_unpaced(args, payloads, (RFI_K, RFI_MIN_BEAMS, BASELINE_R)))
             if rec["serve"]:
                 rec["p99_chunk_latency_s"] = rec["serve"]["p99_s"]
                 if not args.no_cpu_baseline:
@@ -377,6 +384,7 @@ def main():
         if nx:
             rec.update(nx)
         rec["rfi_mask"] = leg("13-beam coincidence mask", 15, lambda: bench_rfi_mask(args))
+    rec["triage"] = leg("triage network, 256 tiles", 20, lambda: bench_triage(args))
     legs["total"] = round(time.perf_counter() - T_START, 1)
     print(json.dumps(rec), flush=True)
 
@@ -557,6 +565,19 @@ def bench_multibeam(args, cpu=None):
         torch.cuda.synchronize()
         per.append(time.perf_counter() - t0)
     t_batch = float(np.mean(per))
+    # the same batch with the pipeline's optional stages: coincidence mask
+    # before dedispersion (over the 2^17 samples all beams share), baseline
+    # removal after
+    L.dedisp_batch_set_stages(batch, RFI_K, RFI_MIN_BEAMS, BASELINE_R)
+    L.dedisp_batch_execute(batch, ins, ns, outs, evs, cap)      # capture + warm-up
+    torch.cuda.synchronize()
+    per_st = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        counts_st = L.dedisp_batch_execute(batch, ins, ns, outs, evs, cap)
+        torch.cuda.synchronize()
+        per_st.append(time.perf_counter() - t0)
+    L.dedisp_batch_set_stages(batch, 0.0, 0, 0)
     # the same work as 13 sequential single-beam calls (the same tile)
     wss = [torch.empty(L.dedisp_workspace_bytes(p, n), dtype=torch.uint8, device="cuda")
            for p, n in zip(plans, ns)]
@@ -591,6 +612,12 @@ def bench_multibeam(args, cpu=None):
            "dm_trial_samples_per_s_batch": dm_samples / t_batch,
            "channel_adds_per_launch": adds,
            "events": int(sum(counts)),
+           "with_stages": {"ms_batch": float(np.mean(per_st)) * 1e3,
+                           "ms_batch_median": pct(per_st, 50) * 1e3,
+                           "rtf": beam_s / (len(plans) * float(np.mean(per_st))),
+                           "events": int(sum(counts_st)),
+                           "rfi_mask": {"k_sigma": RFI_K, "min_beams": RFI_MIN_BEAMS},
+                           "baseline_radius": BASELINE_R},
            "rtf_definition": "sum_b nsamps_b * tsamp / (13 * T_wall)",
            "data": "one seeded fast-noise pool of 2^19 samples with 20 pulses; beam b reads "
                    "its first nsamps_b samples"}
@@ -623,7 +650,7 @@ def _served_recall(results, payloads, plan, tau):
         if sweep is None:
             sweep = np.array([int(synth.sky_arrival_offsets(fb.nchans, fb.f_top, fb.df, fb.tsamp,
                                                             float(d))[-1]) for d in fb.dm_list])
-        off = 0 if r["t_abs0"] == r["seq"] * CHUNK else H     # window offset of the payload
+        off = r["seq"] * CHUNK - r["t_abs0"]     # payload sample 0 in the searched series
         ok = [j for j, p in enumerate(fb.pulses)
               if p.t0 < CHUNK - H and
               p.t0 + p.width + int(synth.sky_arrival_offsets(fb.nchans, fb.f_top, fb.df, fb.tsamp,
@@ -646,13 +673,16 @@ def _served_recall(results, payloads, plan, tau):
                                 "triage = candidates scoring >= tau"}
 
 
-def _serve_run(plans, payloads, model, budget, sched, pace=True, progress_every=0):
+def _serve_run(plans, payloads, model, budget, sched, pace=True, progress_every=0, stages=None):
     """Feed the server on the schedule [(due_ns, beam, seq)] (real-time
-    arrivals when pace, else as fast as it admits); returns (results, stats,
-    wall seconds, busy retries)."""
+    arrivals when pace, else as fast as it admits); `stages` = (rfi k_sigma,
+    rfi min beams, baseline radius) or None; returns (results, stats, wall
+    seconds, busy retries)."""
     from paper_1112_0065_amd import _lib as L
     widths = [1 << i for i in range(10)]
     srv = L.dedisp_serve_create(plans, CHUNK, widths, 6.0, budget, model=model)
+    if stages:
+        L.dedisp_serve_set_stages(srv, *stages)
     t_start = L.dedisp_now_ns()
     done = []
     busy = 0
@@ -702,8 +732,9 @@ def bench_serve(args, payloads):
     period_ns = CHUNK * synth.TSAMP * 1e9 / speed
     sched = sorted((b * period_ns / 13 + (k + 1) * period_ns, b, k)
                    for b in range(13) for k in range(nchunks))
+    stages = (RFI_K, RFI_MIN_BEAMS, 0) if args.serve_rfi else None
     done, st, wall, busy = _serve_run(plans, payloads, model, 32 << 30, sched, pace=True,
-                                      progress_every=13)
+                                      progress_every=13, stages=stages)
     late = sum(1 for r in done if r["flags"] & L.CHUNK_LATE)
     fallback = sum(1 for r in done if r["flags"] & L.CHUNK_FALLBACK)
     lat = np.array([r["done_ns"] - r["arrival_ns"] for r in done], np.float64) * 1e-9
@@ -719,14 +750,59 @@ def bench_serve(args, payloads):
             "events": int(sum(r["n_events"] for r in done)),
             "candidates_scored": int(sum(r["n_candidates"] for r in done)),
             "triage": _served_recall(done, payloads, plans[0], tau),
+            "stages": ({"rfi_mask": {"k_sigma": RFI_K, "min_beams": RFI_MIN_BEAMS},
+                        "note": "each round of 13 chunks (one sequence number) is masked and "
+                                "batched together, so a chunk waits for the round's last "
+                                "(staggered) beam: latency includes up to 12/13 of a chunk"}
+                       if stages else None),
             "data": f"{len(payloads)} interference chunk payloads (make_rfi_beam seeds 400..) "
                     "cycled over beams and sequence numbers"}
 
 
+def _serve_burst(plans, payloads, model, budget, nchunks, threads, stages=None):
+    """Every beam submits its chunks as fast as the server admits them, from
+    `threads` submitting threads (beam b on thread b % threads, each beam in
+    sequence order; BUSY is retried): the arrival rate exceeds what the
+    slots drain, so admission queues.  Returns (results, stats, wall
+    seconds, busy retries)."""
+    import threading
+
+    from paper_1112_0065_amd import _lib as L
+    widths = [1 << i for i in range(10)]
+    srv = L.dedisp_serve_create(plans, CHUNK, widths, 6.0, budget, model=model)
+    if stages:
+        L.dedisp_serve_set_stages(srv, *stages)
+    busy = [0] * threads
+
+    def feed(t):
+        for k in range(nchunks):
+            for b in range(t, len(plans), threads):
+                while not L.dedisp_serve_submit(srv, b, k, payloads[(b + k) % len(payloads)].packed,
+                                                L.dedisp_now_ns()):
+                    busy[t] += 1
+                    time.sleep(0.0002)
+
+    t_start = L.dedisp_now_ns()
+    ths = [threading.Thread(target=feed, args=(t,)) for t in range(threads)]
+    for th in ths:
+        th.start()
+    done = []
+    want = nchunks * len(plans)
+    while len(done) < want:
+        done += L.dedisp_serve_poll(srv, 64, 100)
+    for th in ths:
+        th.join()
+    wall = (L.dedisp_now_ns() - t_start) * 1e-9
+    st = L.dedisp_serve_stats(srv)
+    srv.close()
+    return done, st, wall, sum(busy)
+
+
 def bench_serve_queueing(args, payloads):
     """The same 13 beams with an HBM budget of the resident overlaps plus 3
-    chunk slots, every chunk submitted as soon as the server admits it (4 per
-    beam): admission holds the rest back (BUSY) and batches never exceed 3."""
+    chunk slots, 4 chunks per beam submitted from 4 threads as fast as the
+    server admits them: admission holds the rest back (BUSY) and every batch
+    takes the slots that have drained (at most 3 chunks)."""
     import synth
     from paper_1112_0065_amd import _lib as L
     from paper_1112_0065_amd import triage_train as T
@@ -737,8 +813,7 @@ def bench_serve_queueing(args, payloads):
     slot = L.dedisp_serve_slot_bytes(plans, CHUNK, widths)
     resident = sum((p.max_delay + 511) * 256 for p in plans)
     budget = resident + 3 * slot + slot // 2
-    sched = [(0, b, k) for k in range(4) for b in range(13)]
-    done, st, wall, busy = _serve_run(plans, payloads, model, budget, sched, pace=False)
+    done, st, wall, busy = _serve_burst(plans, payloads, model, budget, 4, 4)
     beam_s = 13 * 4 * CHUNK * synth.TSAMP
     return {"beams": 13, "chunks": len(done), "slots": st["slots"],
             "budget_bytes": budget, "slot_bytes": slot, "busy_retries": busy,
@@ -747,23 +822,26 @@ def bench_serve_queueing(args, payloads):
             "wall_s": wall, "rtf": beam_s / (13 * wall)}
 
 
-def bench_serve_unpaced(args, payloads):
+def bench_serve_unpaced(args, payloads, stages=None):
     """The same 13-beam server (no triage) fed as fast as it accepts chunks
-    (BUSY = back-pressure, retried): the sustained real-time factor of
-    streaming, sum of beam-seconds / (13 T_wall), with continuous batching of
-    whatever is queued."""
+    (4 submitting threads, BUSY = back-pressure, retried): the sustained
+    real-time factor of streaming, sum of beam-seconds / (13 T_wall), with
+    continuous batching of whatever is queued; `stages` as for _serve_run."""
     import synth
 
     plans = _serve_plans()
     nchunks = args.serve_unpaced_chunks
-    sched = [(0, b, k) for k in range(nchunks) for b in range(13)]
-    done, st, wall, busy = _serve_run(plans, payloads, None, 32 << 30, sched, pace=False)
+    done, st, wall, busy = _serve_burst(plans, payloads, None, 32 << 30, nchunks, 4, stages)
     beam_s = 13 * nchunks * CHUNK * synth.TSAMP
-    return {"beams": 13, "chunks": len(done), "beam_seconds": beam_s, "wall_s": wall,
-            "rtf": beam_s / (13 * wall), "beam_seconds_per_s": beam_s / wall,
-            "batches": st["batches"], "mean_batch": st["mean_batch"],
-            "max_batch": st["max_batch"], "slots": st["slots"], "busy_retries": busy,
-            "p50_s": st["p50_ns"] * 1e-9, "p99_s": st["p99_ns"] * 1e-9}
+    res = {"beams": 13, "chunks": len(done), "beam_seconds": beam_s, "wall_s": wall,
+           "rtf": beam_s / (13 * wall), "beam_seconds_per_s": beam_s / wall,
+           "batches": st["batches"], "mean_batch": st["mean_batch"],
+           "max_batch": st["max_batch"], "slots": st["slots"], "busy_retries": busy,
+           "p50_s": st["p50_ns"] * 1e-9, "p99_s": st["p99_ns"] * 1e-9}
+    if stages:
+        res["stages"] = {"rfi_mask": {"k_sigma": stages[0], "min_beams": stages[1]},
+                         "baseline_radius": stages[2]}
+    return res
 
 
 def bench_subband(fb, plan, inp, ev_direct, direct_ms, cpu=False):
@@ -835,6 +913,67 @@ def bench_subband(fb, plan, inp, ev_direct, direct_ms, cpu=False):
         del ws, out, pws, eb
         sb.close()
         torch.cuda.empty_cache()
+    return res
+
+
+# Multiply-adds of the triage network per 64 x 256 tile (3x3 convolutions at
+# 64x256, 32x128, 16x64 and 8x32 with 1->32->32->32->32 channels; pooling,
+# bias and the final layer are negligible), counted as 2 FLOP each.
+TRIAGE_FWD_FLOP = 2 * 9 * 32 * (1 * 64 * 256 + 32 * 32 * 128 + 32 * 16 * 64 + 32 * 8 * 32)
+
+
+def bench_triage(args, reps=20, n=256):
+    """The triage network on one batch of 256 seeded candidate tiles: scoring
+    (forward) and a training step (forward, input- and weight-gradients,
+    Adam), each timed with HIP events on the stream it runs on; achieved
+    TFLOP/s with the training step counted as three forward passes.  The CPU
+    leg times the oracle's forward and backward on 16 of the tiles."""
+    import numpy as np
+    import torch
+
+    from paper_1112_0065_amd import _lib as L
+
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((n, 64, 256)).astype(np.float32)
+    x[::2, 28:36, 100:160] += 3.0
+    tiles = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).cuda()
+    labels = torch.tensor([1.0, 0.0] * (n // 2), dtype=torch.float32, device="cuda")
+    scores = torch.empty(n, dtype=torch.float32, device="cuda")
+    m = L.triage_create(None, 0)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    fwd_ms = timed(lambda: L.triage_score(m, tiles, n, scores, stream))
+    train_ms = timed(lambda: L.triage_train_step(m, tiles, labels, n, 1e-4, stream))
+    fwd_flop = TRIAGE_FWD_FLOP * n
+    res = {"tiles": n, "forward_ms": fwd_ms, "train_step_ms": train_ms,
+           "forward_flop_per_tile": TRIAGE_FWD_FLOP,
+           "forward_tflops": fwd_flop / (fwd_ms * 1e-3) / 1e12,
+           "train_tflops": 3 * fwd_flop / (train_ms * 1e-3) / 1e12,
+           "peak_bf16_tflops": 2500.0,
+           "tiles_per_s_scoring": n / (fwd_ms * 1e-3)}
+    res["forward_frac_of_bf16_peak"] = res["forward_tflops"] / 2500.0
+    if not args.no_cpu_baseline:
+        from oracle import cnn
+        p = cnn.init_params(0)
+        k = 16
+        t_c = time.perf_counter()
+        logits, cache = cnn.forward(p, cnn.round_bf16(x[:k].astype(np.float64)))
+        cnn.backward(p, cache, logits, np.array([1.0, 0.0] * (k // 2)))
+        t_c = time.perf_counter() - t_c
+        res["cpu_oracle"] = {"value": k / t_c, "unit": "tiles/s (forward + backward)", "cores": 1,
+                             "kind": "oracle", "sample": f"{k} of the {n} tiles ({t_c:.2f} s)"}
+    del m
     return res
 
 
