@@ -7,9 +7,10 @@
 // fallback.  Layout: activations NHWC bfloat16 (channels innermost, 64 bytes
 // per pixel), float32 accumulation.  The 32->32 convolutions (forward and
 // input gradient) are implicit GEMMs on the bf16 matrix cores
-// (v_mfma_f32_16x16x16_bf16: M = pixels, N = 32 output channels,
-// K = 9 taps x 32 input channels = 288); the weight gradient is a GEMM over
-// pixels (M = 32, N = 32 per tap, K = pixels) on the same instruction,
+// (v_mfma_f32_16x16x32_bf16, gfx950's double-K form: M = pixels, N = 32
+// output channels, K = 9 taps x 32 input channels = 288, one tap per step);
+// the weight gradient is a GEMM over pixels (M = 32, N = 32 per tap,
+// K = pixels, 32 per step) on the same instruction,
 // reduced across blocks in a fixed order (no float atomics: training is
 // reproducible bit for bit).  The 1->32 first layer (K = 9) runs on VALU.
 #include <cstdint>
@@ -19,6 +20,7 @@
 namespace tk {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -27,6 +29,19 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
     return static_cast<uint16_t>(u >> 16);
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
+
+// Eight consecutive bf16 values (16 bytes, 16-byte aligned).
+__device__ __forceinline__ bf16x8 load8(const uint16_t* p) {
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
+}
+
+__device__ __forceinline__ bf16x8 pack8(const uint16_t (&v)[8]) {
+    const uint4 u = make_uint4(v[0] | (static_cast<uint32_t>(v[1]) << 16),
+                               v[2] | (static_cast<uint32_t>(v[3]) << 16),
+                               v[4] | (static_cast<uint32_t>(v[5]) << 16),
+                               v[6] | (static_cast<uint32_t>(v[7]) << 16));
+    return __builtin_bit_cast(bf16x8, u);
+}
 
 __device__ __forceinline__ bf16x4 load4(const uint16_t* p) {
     const uint2 v = *reinterpret_cast<const uint2*>(p);
@@ -117,8 +132,8 @@ __global__ __launch_bounds__(256) void conv1_fwd_kernel(const uint16_t* __restri
 
 // ---------------------------------------------------------------------------
 // 32 -> 32 convolution as an implicit GEMM on MFMA.  One wave = 32 pixels of
-// one image row x 32 output channels (2 x 2 tiles of 16 x 16), K = 288 in 18
-// steps of 16 (one tap, half of the input channels, per step).
+// one image row x 32 output channels (2 x 2 tiles of 16 x 16), K = 288 in 9
+// steps of 32 (one tap, all 32 input channels, per step).
 // MODE 0: out = bf16(ReLU(acc + bias)); MODE 1: out = acc (float32).
 // wt: [co][tap][ci] bf16 (forward) or the flipped, transposed kernel for the
 // input gradient.
@@ -141,26 +156,28 @@ __global__ __launch_bounds__(64) void conv32_mfma_kernel(const uint16_t* __restr
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const bf16x4 zero4 = bf16x4{0, 0, 0, 0};
-#pragma unroll 2
-    for (int s = 0; s < 18; ++s) {
-        const int tap = s >> 1;
-        const int ci0 = 16 * (s & 1) + 4 * kq;
+    const bf16x8 zero8 = __builtin_bit_cast(bf16x8, make_uint4(0u, 0u, 0u, 0u));
+    // one tap (all 32 input channels) per step: lane slice kq holds channels
+    // 8 kq .. 8 kq + 7 of its pixel (A) and of its output channel's tap (B),
+    // one 16-byte load each
+    const int ci0 = 8 * kq;
+#pragma unroll 3
+    for (int tap = 0; tap < 9; ++tap) {
         const int y2 = y + tap / 3 - 1;
-        bf16x4 afr[2], bfr[2];
+        bf16x8 afr[2], bfr[2];
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
             const int x2 = xs + 16 * rt + row + tap % 3 - 1;
             const bool ok = y2 >= 0 && y2 < H && x2 >= 0 && x2 < W;
-            afr[rt] = ok ? load4(x + ((n * H + y2) * W + x2) * kCH + ci0) : zero4;
+            afr[rt] = ok ? load8(x + ((n * H + y2) * W + x2) * kCH + ci0) : zero8;
         }
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) bfr[ct] = load4(wt + ((16 * ct + row) * 9 + tap) * kCH + ci0);
+        for (int ct = 0; ct < 2; ++ct) bfr[ct] = load8(wt + ((16 * ct + row) * 9 + tap) * kCH + ci0);
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct)
-                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(afr[rt], bfr[ct], acc[rt][ct], 0, 0, 0);
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[rt], bfr[ct], acc[rt][ct], 0, 0, 0);
     }
     // D[i][c]: lane holds rows 4*kq + j (pixels), column row (channel)
 #pragma unroll
@@ -292,7 +309,7 @@ __global__ void pool_relu_bwd_kernel(const float* __restrict__ dp, const uint8_t
 
 // Weight gradient of a 32 -> 32 layer for one tap, over `rows` consecutive
 // image rows per block: dW_tap[co][ci] = sum_pixels dz[p][co] x[p + tap][ci].
-// MFMA with M = co, N = ci, K = pixels (16 per step).  Writes one partial per
+// MFMA with M = co, N = ci, K = pixels (32 per step).  Writes one partial per
 // block: part[blk][tap][co][ci].
 __global__ __launch_bounds__(64) void wgrad32_mfma_kernel(const uint16_t* __restrict__ x,
                                                           const uint16_t* __restrict__ dz, int N,
@@ -315,34 +332,35 @@ __global__ __launch_bounds__(64) void wgrad32_mfma_kernel(const uint16_t* __rest
         const int64_t n = rr / H;
         const int y2 = y + ky;
         const bool yok = y2 >= 0 && y2 < H;
-        for (int x0 = 0; x0 < W; x0 += 16) {
-            bf16x4 afr[2], bfr[2];
-            // A[co][k = pixel]: 4 consecutive pixels of one output channel
+        for (int x0 = 0; x0 < W; x0 += 32) {
+            bf16x8 afr[2], bfr[2];
+            // A[co][k = pixel]: 8 consecutive pixels of one output channel
 #pragma unroll
             for (int rt = 0; rt < 2; ++rt) {
                 const int co = 16 * rt + idx16;
+                uint16_t v[8];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int xp = x0 + 4 * kq + j;
-                    afr[rt][j] = static_cast<short>(dz[((n * H + y) * W + xp) * kCH + co]);
-                }
+                for (int j = 0; j < 8; ++j) v[j] = dz[((n * H + y) * W + x0 + 8 * kq + j) * kCH + co];
+                afr[rt] = pack8(v);
             }
             // B[k = pixel][ci]: shifted input
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct) {
                 const int ci = 16 * ct + idx16;
+                uint16_t v[8];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int x2 = x0 + 4 * kq + j + kx;
+                for (int j = 0; j < 8; ++j) {
+                    const int x2 = x0 + 8 * kq + j + kx;
                     const bool ok = yok && x2 >= 0 && x2 < W;
-                    bfr[ct][j] = ok ? static_cast<short>(x[((n * H + y2) * W + x2) * kCH + ci]) : short(0);
+                    v[j] = ok ? x[((n * H + y2) * W + x2) * kCH + ci] : uint16_t(0);
                 }
+                bfr[ct] = pack8(v);
             }
 #pragma unroll
             for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
                 for (int ct = 0; ct < 2; ++ct)
-                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(afr[rt], bfr[ct], acc[rt][ct], 0, 0, 0);
+                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[rt], bfr[ct], acc[rt][ct], 0, 0, 0);
         }
     }
     float* dst = part + (static_cast<int64_t>(blockIdx.x) * 9 + tap) * kCH * kCH;
