@@ -85,4 +85,33 @@ BS_HD void planes_to_pairs(const uint32_t (&a)[NL], uint32_t (&r)[16]) {
     }
 }
 
+// Carry-in at level F: add the planes p and c (weight 2^F each) to the
+// counter levels F..NL-1 (one full adder, then a half-adder ripple).  Sums
+// never exceed 2^NL - 1, so the top level drops its (zero) carry.
+template <int NL, int F>
+BS_HD void carry_in2(uint32_t (&a)[NL], uint32_t p, uint32_t c) {
+    uint32_t k = BS_MAJ3(a[F], p, c);
+    a[F] = BS_XOR3(a[F], p, c);
+#pragma unroll
+    for (int l = F + 1; l < NL - 1; ++l) {
+        const uint32_t t = a[l] & k;
+        a[l] ^= k;
+        k = t;
+    }
+    a[NL - 1] ^= k;
+}
+
+// Carry-in of one plane c at level F.
+template <int NL, int F>
+BS_HD void carry_in1(uint32_t (&a)[NL], uint32_t c) {
+    uint32_t k = c;
+#pragma unroll
+    for (int l = F; l < NL - 1; ++l) {
+        const uint32_t t = a[l] & k;
+        a[l] ^= k;
+        k = t;
+    }
+    a[NL - 1] ^= k;
+}
+
 }  // namespace bs

@@ -75,6 +75,19 @@ DD_CSA_SPEC(12, 4) DD_CSA_SPEC(12, 8) DD_CSA_SPEC(12, 16) DD_CSA_SPEC(12, 32)
 DD_CSA_SPEC(16, 4) DD_CSA_SPEC(16, 8) DD_CSA_SPEC(16, 16) DD_CSA_SPEC(16, 32)
 #undef DD_CSA_SPEC
 
+// Low counter of 5 levels per chunk (see gen_csa.py): the chunk's carry-out
+// plane of weight 32 waits in `pend` for the next chunk's, and the two enter
+// the upper levels together -- one ripple per two chunks instead of one per
+// chunk.
+template <int NL, int N>
+__device__ __forceinline__ uint32_t csa_low(uint32_t (&a)[NL], const uint32_t (&lo)[N],
+                                            const uint32_t (&hi)[N]) {
+    if constexpr (N == 8)
+        return csa5_add_8<NL>(a, lo, hi);
+    else
+        return csa5_add_4<NL>(a, lo, hi);
+}
+
 // Accumulate channels [c, c+N) of the current stage for one trial into the
 // counters of its G groups.
 // The trial's offset-table row gives, per channel, the LDS byte offset of the
@@ -82,9 +95,9 @@ DD_CSA_SPEC(16, 4) DD_CSA_SPEC(16, 8) DD_CSA_SPEC(16, 16) DD_CSA_SPEC(16, 32)
 // which is all the shift instruction reads).  A quad is a 16-byte aligned
 // copy of two consecutive words, so each (trial, channel, group) is one
 // aligned 16-byte LDS read.
-template <int NL, int G, int N>
-__device__ __forceinline__ void accumulate_chunk(uint32_t (&acc)[G][NL], const char* lds_lane,
-                                                 cptr<uint32_t> trow, int c) {
+template <int NL, int G, int N, bool ODD>
+__device__ __forceinline__ void accumulate_chunk(uint32_t (&acc)[G][NL], uint32_t (&pend)[G],
+                                                 const char* lds_lane, cptr<uint32_t> trow, int c) {
     uint32_t e[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) e[k] = trow[c + k];
@@ -101,8 +114,22 @@ __device__ __forceinline__ void accumulate_chunk(uint32_t (&acc)[G][NL], const c
             lo[k] = bs::funnel(w[k].z, w[k].x, e[k]);
             hi[k] = bs::funnel(w[k].w, w[k].y, e[k]);
         }
-        csa_add<NL, N>(acc[g], lo, hi);
+        const uint32_t cy = csa_low<NL, N>(acc[g], lo, hi);
+        if (ODD)
+            bs::carry_in2<NL, 5>(acc[g], pend[g], cy);
+        else
+            pend[g] = cy;
     }
+}
+
+// One chunk, completing a pair of carry-outs when it is the second of two.
+template <int NL, int G, int N>
+__device__ __forceinline__ void chunk(uint32_t (&acc)[G][NL], uint32_t (&pend)[G], int k,
+                                      const char* lds_lane, cptr<uint32_t> trow, int c) {
+    if (k & 1)
+        accumulate_chunk<NL, G, N, true>(acc, pend, lds_lane, trow, c);
+    else
+        accumulate_chunk<NL, G, N, false>(acc, pend, lds_lane, trow, c);
 }
 
 // Asynchronous copy of one LDS stage: channels [c0, c0 + cs) of the block's
@@ -122,13 +149,19 @@ __device__ __forceinline__ void fill_stage(const dd::BeamArgs& a, cptr<int32_t> 
         const int64_t w0 = w_base + (dlo_row[c] >> 5);
         const int64_t avail = a.nwords - w0;   // > 0: w0 < nsamps / 32 + 1 < nwords
         const int nq = static_cast<int>((avail < stride ? avail : stride) - 1);
+        // uniform source row; each lane adds its own 8-byte word offset
         const uint2* src = a.words + static_cast<int64_t>(c) * a.nwords + w0;
         char* dst = lds + static_cast<int64_t>(cl) * a.pitch * 16;
         for (int i = 0; i < nq; i += 64) {
-            if (i + lane < nq)
-                __builtin_amdgcn_global_load_lds(
-                    (const __attribute__((address_space(1))) void*)(src + i + lane),
-                    (__attribute__((address_space(3))) void*)(dst + 16 * i), 16, 0, 0);
+            // full batches of 64 quads need no per-lane check
+            const uint2* s = src + i;
+            char* q = dst + 16 * i;
+            if (i + 64 <= nq)
+                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(s + lane),
+                                                 (__attribute__((address_space(3))) void*)q, 16, 0, 0);
+            else if (lane < nq - i)
+                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(s + lane),
+                                                 (__attribute__((address_space(3))) void*)q, 16, 0, 0);
         }
     }
 }
@@ -138,6 +171,7 @@ __device__ __forceinline__ void fill_stage(const dd::BeamArgs& a, cptr<int32_t> 
 // pointers so the compiler knows the LDS reads do not wait on the copy.
 template <int NL, int NDW, int G>
 __device__ __forceinline__ void run_stage(const dd::BeamArgs& a, uint32_t (&acc)[NDW][G][NL],
+                                          uint32_t (&pend)[NDW][G], int kbase,
                                           cptr<int32_t> dlo_row, int64_t w_base, int stride,
                                           int c0, int stage_chans, int d_lo,
                                           const char* __restrict__ cur, char* __restrict__ nxt,
@@ -151,12 +185,32 @@ __device__ __forceinline__ void run_stage(const dd::BeamArgs& a, uint32_t (&acc)
         const int d = d_lo + wave + kWaves * i;
         if (d < a.ndm) {
             const cptr<uint32_t> trow = as_const(a.offs) + static_cast<int64_t>(d) * a.nchans;
-            int cl = 0;
+            int cl = 0, k = kbase;
             // 8-channel steps: fewer live registers than 16, more resident waves
 #pragma unroll 1
-            for (; cl + 8 <= cs; cl += 8)
-                accumulate_chunk<NL, G, 8>(acc[i], cur + 16 * lane, trow, c0 + cl);
-            if (cl + 4 <= cs) accumulate_chunk<NL, G, 4>(acc[i], cur + 16 * lane, trow, c0 + cl);
+            for (; cl + 8 <= cs; cl += 8, ++k)
+                chunk<NL, G, 8>(acc[i], pend[i], k, cur + 16 * lane, trow, c0 + cl);
+            if (cl + 4 <= cs) chunk<NL, G, 4>(acc[i], pend[i], k, cur + 16 * lane, trow, c0 + cl);
+        }
+    }
+}
+
+// One stage of exactly 8 channels: start the copy of the next stage, then add
+// this stage's 8-channel chunk for every trial.  SECOND: the chunk is the
+// second of a pair (its carry-out joins the first one's).
+template <int NL, int NDW, int G, bool SECOND>
+__device__ __forceinline__ void stage8(const dd::BeamArgs& a, uint32_t (&acc)[NDW][G][NL],
+                                       uint32_t (&pend)[NDW][G], cptr<int32_t> dlo_row,
+                                       int64_t w_base, int stride, int c0, int d_lo,
+                                       const char* __restrict__ cur, char* __restrict__ nxt,
+                                       bool more, int lane, int wave) {
+    if (more) fill_stage(a, dlo_row, w_base, stride, c0 + 8, 8, nxt, lane, wave);
+#pragma unroll
+    for (int i = 0; i < NDW; ++i) {
+        const int d = d_lo + wave + kWaves * i;
+        if (d < a.ndm) {
+            const cptr<uint32_t> trow = as_const(a.offs) + static_cast<int64_t>(d) * a.nchans;
+            accumulate_chunk<NL, G, 8, SECOND>(acc[i], pend[i], cur + 16 * lane, trow, c0);
         }
     }
 }
@@ -167,7 +221,7 @@ __device__ __forceinline__ void run_stage(const dd::BeamArgs& a, uint32_t (&acc)
 // buffer s & 1, so channel c sits in row c mod (2 * stage_chans) -- the row
 // the offset table assumes.  While the waves work on stage s, the copy of
 // stage s + 1 into the other buffer is in flight.
-template <int NL, int NDW, int G, bool OUT16>
+template <int NL, int NDW, int G, bool OUT16, bool S8>
 __device__ __forceinline__ void process_item(const dd::BeamArgs& a, int tile, int dblk,
                                              int stage_chans, char* lds, int lane, int wave) {
     constexpr int ND = NDW * kWaves;
@@ -181,26 +235,64 @@ __device__ __forceinline__ void process_item(const dd::BeamArgs& a, int tile, in
     const int nst = (a.nchans + stage_chans - 1) / stage_chans;
 
     uint32_t acc[NDW][G][NL];
+    uint32_t pend[NDW][G];
 #pragma unroll
     for (int i = 0; i < NDW; ++i)
 #pragma unroll
-        for (int g = 0; g < G; ++g)
+        for (int g = 0; g < G; ++g) {
+            pend[i][g] = 0u;
 #pragma unroll
             for (int l = 0; l < NL; ++l) acc[i][g][l] = 0u;
+        }
+    int kbase = 0;   // chunks added so far (the same for every trial)
 
     fill_stage(a, dlo_row, w_base, stride, 0, min(stage_chans, a.nchans), lds, lane, wave);
     const int64_t half = static_cast<int64_t>(stage_chans) * a.pitch * 16;   // bytes
+    if (S8) {
+        // stages of 8 channels, every one full: pairs of stages, the first in
+        // buffer 0 and the second in buffer 1, so the pairing of carry-outs
+        // and the buffers are fixed in the code
+        int st = 0;
 #pragma unroll 1
-    for (int st = 0; st < nst; ++st) {
+        for (; st + 1 < nst; st += 2) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            stage8<NL, NDW, G, false>(a, acc, pend, dlo_row, w_base, stride, 8 * st, d_lo, lds,
+                                      lds + half, true, lane, wave);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            stage8<NL, NDW, G, true>(a, acc, pend, dlo_row, w_base, stride, 8 * st + 8, d_lo,
+                                     lds + half, lds, st + 2 < nst, lane, wave);
+        }
+        kbase = st;
+        if (st < nst) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            stage8<NL, NDW, G, false>(a, acc, pend, dlo_row, w_base, stride, 8 * st, d_lo, lds,
+                                      lds + half, false, lane, wave);
+            kbase = nst;
+        }
+    }
+#pragma unroll 1
+    for (int st = 0; st < (S8 ? 0 : nst); ++st) {
         const int c0 = st * stage_chans;
         // this wave's copies of stage st are done; after the barrier every
         // wave's are, and every wave has finished stage st - 1, whose buffer
         // the copy of stage st + 1 now overwrites
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        run_stage<NL, NDW, G>(a, acc, dlo_row, w_base, stride, c0, stage_chans, d_lo,
+        run_stage<NL, NDW, G>(a, acc, pend, kbase, dlo_row, w_base, stride, c0, stage_chans, d_lo,
                               (st & 1) ? lds + half : lds, (st & 1) ? lds : lds + half,
                               st + 1 < nst, lane, wave);
+        const int cs = min(stage_chans, a.nchans - c0);
+        kbase += cs / 8 + ((cs & 4) ? 1 : 0);
+    }
+    // an odd number of chunks leaves one carry-out waiting
+    if (kbase & 1) {
+#pragma unroll
+        for (int i = 0; i < NDW; ++i)
+#pragma unroll
+            for (int g = 0; g < G; ++g) bs::carry_in1<NL, 5>(acc[i][g], pend[i][g]);
     }
 
     // Write: counters -> integers, one 32-sample group per lane and group.
@@ -284,8 +376,12 @@ __global__ __launch_bounds__(kThreads) void dedisperse_kernel(dd::BeamArgs a, in
     if (item >= n_items) return;
     int tile, dblk;
     item_coords(a, item, &tile, &dblk);
-    process_item<NL, NDW, G, OUT16>(a, tile, dblk, stage_chans, reinterpret_cast<char*>(lds), lane,
-                                    wave);
+    if (stage_chans == 8 && (a.nchans & 7) == 0)
+        process_item<NL, NDW, G, OUT16, true>(a, tile, dblk, 8, reinterpret_cast<char*>(lds), lane,
+                                              wave);
+    else
+        process_item<NL, NDW, G, OUT16, false>(a, tile, dblk, stage_chans,
+                                               reinterpret_cast<char*>(lds), lane, wave);
 }
 
 // Persistent form over the work items of several beams: blocks pop items
@@ -322,8 +418,12 @@ __global__ __launch_bounds__(kThreads) void dedisperse_persistent_kernel(
         const int64_t local = item - a.item_begin;
         int tile, dblk;
         item_coords(a, local, &tile, &dblk);
-        process_item<NL, NDW, G, OUT16>(a, tile, dblk, stage_chans, reinterpret_cast<char*>(lds),
-                                        lane, wave);
+        if (stage_chans == 8 && (a.nchans & 7) == 0)
+            process_item<NL, NDW, G, OUT16, true>(a, tile, dblk, 8, reinterpret_cast<char*>(lds),
+                                                  lane, wave);
+        else
+            process_item<NL, NDW, G, OUT16, false>(a, tile, dblk, stage_chans,
+                                                   reinterpret_cast<char*>(lds), lane, wave);
     }
 }
 

@@ -78,6 +78,61 @@ class Emitter:
                 self.push(level + 1, cy)
 
 
+class FastEmitter(Emitter):
+    """Low counter of FAST levels only: a bit pushed to level FAST is the
+    chunk's carry-out, returned instead of rippled further.  The low counter
+    holds at most 2^FAST - 1 and a chunk of n channels adds at most 3 n;
+    while their sum stays below 2^(FAST+1), at most one carry bit per
+    position leaves the low counter, so the carry-out planes the tree makes
+    are disjoint and merge with XOR."""
+
+    def __init__(self, fast):
+        super().__init__(fast + 1)
+        self.fast = fast
+        self.outs = []
+
+    def push(self, level, x):
+        if level == self.fast:
+            self.outs.append(x)
+            return
+        if self.pending[level] is None:
+            self.pending[level] = x
+            return
+        p = self.pending[level]
+        self.pending[level] = None
+        cy = self.full_add(level, p, x)
+        self.push(level + 1, cy)
+
+    def flush(self):
+        for level in range(self.fast):
+            p = self.pending[level]
+            if p is None:
+                continue
+            self.pending[level] = None
+            cy = self.half_add(level, p)
+            self.push(level + 1, cy)
+
+
+FAST = 5          # levels of the low counter
+FAST_SIZES = (4, 8)
+
+
+def emit_fast(n):
+    assert 3 * n + 2 ** FAST - 1 < 2 ** (FAST + 1), "one carry-out per chunk"
+    e = FastEmitter(FAST)
+    for c in range(n):
+        e.push(0, f"lo[{c}]")
+        e.push(1, f"hi[{c}]")
+    e.flush()
+    outs = e.outs
+    ret = outs[0] if outs else "0u"
+    for o in outs[1:]:
+        ret = f"({ret} ^ {o})"
+    head = (f"template <int NL>\nstatic __host__ __device__ __forceinline__ uint32_t csa{FAST}_add_{n}"
+            f"(uint32_t (&a)[NL], const uint32_t (&lo)[{n}], const uint32_t (&hi)[{n}])\n{{")
+    return "\n".join([head] + e.lines + [f"  return {ret};", "}\n"])
+
+
 def emit(n, nl):
     e = Emitter(nl)
     for c in range(n):
@@ -96,6 +151,10 @@ def main():
     for nl in (12, 16):
         for n in SIZES:
             out.append(emit(n, nl))
+    out.append(f"// Low-counter trees: add n channels into levels 0..{FAST - 1} of a[] and")
+    out.append(f"// return the carry-out plane of weight 2^{FAST} (see FastEmitter).")
+    for n in FAST_SIZES:
+        out.append(emit_fast(n))
     sys.stdout.write("\n".join(out))
 
 

@@ -1,6 +1,8 @@
 """Host-side checks that need no GPU: the built library loads and exports
 every symbol the header declares, and the bit-sliced integer helpers the
-dedispersion kernel uses are exact (compiled for the CPU with g++)."""
+dedispersion kernel uses -- carry-save trees, the low counter with paired
+carry-outs, the plane transpose -- are exact (compiled for the CPU with
+g++)."""
 import ctypes
 import os
 import subprocess
@@ -79,6 +81,46 @@ int check(std::mt19937& rng, int reps) {
     return 0;
 }
 
+// The kernel's pairing: each chunk of 8 (or 4) channels goes into the 5-level
+// low counter; its carry-out waits for the next chunk's and the two enter the
+// upper levels together; an odd last one enters alone.
+template <int NL>
+int check_pairs(std::mt19937& rng, int reps) {
+    for (int rep = 0; rep < reps; ++rep) {
+        uint32_t a[NL] = {0};
+        uint32_t pend = 0;
+        int ref[32] = {0};
+        const int nchunks = 1 + rng() % ((NL == 12 ? 1364 : 21844) / 8);
+        int k = 0;
+        for (int ci = 0; ci < nchunks; ++ci, ++k) {
+            const bool four = (rng() % 5) == 0;
+            uint32_t lo[8], hi[8];
+            const int n = four ? 4 : 8;
+            for (int j = 0; j < n; ++j) {
+                lo[j] = rng(); hi[j] = rng();
+                if (rep % 3 == 0) { lo[j] = hi[j] = 0xFFFFFFFFu; }
+                for (int b = 0; b < 32; ++b) ref[b] += ((lo[j] >> b) & 1) + 2 * ((hi[j] >> b) & 1);
+            }
+            uint32_t cy;
+            if (four) {
+                uint32_t l4[4] = {lo[0], lo[1], lo[2], lo[3]}, h4[4] = {hi[0], hi[1], hi[2], hi[3]};
+                cy = csa5_add_4<NL>(a, l4, h4);
+            } else {
+                cy = csa5_add_8<NL>(a, lo, hi);
+            }
+            if (k & 1) bs::carry_in2<NL, 5>(a, pend, cy); else pend = cy;
+        }
+        if (k & 1) bs::carry_in1<NL, 5>(a, pend);
+        uint32_t r[16];
+        bs::planes_to_pairs<NL>(a, r);
+        for (int b = 0; b < 32; ++b) {
+            const uint32_t v = b < 16 ? (r[b] & 0xFFFF) : (r[b - 16] >> 16);
+            if ((int)v != ref[b]) { printf("FAIL pairs NL=%d rep=%d b=%d got %u want %d\n", NL, rep, b, v, ref[b]); return 1; }
+        }
+    }
+    return 0;
+}
+
 int funnel_check(std::mt19937& rng) {
     for (int i = 0; i < 1000; ++i) {
         uint32_t hi = rng(), lo = rng(), r = rng() % 32;
@@ -94,6 +136,7 @@ int main() {
     bad |= check<12, 4>(rng, 30); bad |= check<12, 8>(rng, 30); bad |= check<12, 16>(rng, 30);
     bad |= check<12, 32>(rng, 30); bad |= check<12, 64>(rng, 10);
     bad |= check<16, 4>(rng, 6); bad |= check<16, 16>(rng, 6); bad |= check<16, 32>(rng, 6);
+    bad |= check_pairs<12>(rng, 60); bad |= check_pairs<16>(rng, 8);
     printf(bad ? "FAILED\n" : "ALL OK\n");
     return bad;
 }
