@@ -88,16 +88,28 @@ BS_HD void planes_to_pairs(const uint32_t (&a)[NL], uint32_t (&r)[16]) {
 // Carry-in at level F: add the planes p and c (weight 2^F each) to the
 // counter levels F..NL-1 (one full adder, then a half-adder ripple).  Sums
 // never exceed 2^NL - 1, so the top level drops its (zero) carry.
+// One half adder in place: a ^= k, k = old a & k.  On the device the two
+// operations are kept as written (the compiler would otherwise fold pairs of
+// levels into three-input operations whose results land in fresh registers,
+// and a loop-carried counter then pays a copy per level).
+BS_HD void half_add(uint32_t& a, uint32_t& k) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t t;
+    asm volatile("v_and_b32 %0, %1, %2\n\tv_xor_b32 %1, %1, %2" : "=&v"(t), "+v"(a) : "v"(k));
+    k = t;
+#else
+    const uint32_t t = a & k;
+    a ^= k;
+    k = t;
+#endif
+}
+
 template <int NL, int F>
 BS_HD void carry_in2(uint32_t (&a)[NL], uint32_t p, uint32_t c) {
     uint32_t k = BS_MAJ3(a[F], p, c);
     a[F] = BS_XOR3(a[F], p, c);
 #pragma unroll
-    for (int l = F + 1; l < NL - 1; ++l) {
-        const uint32_t t = a[l] & k;
-        a[l] ^= k;
-        k = t;
-    }
+    for (int l = F + 1; l < NL - 1; ++l) half_add(a[l], k);
     a[NL - 1] ^= k;
 }
 

@@ -207,10 +207,19 @@ __device__ __forceinline__ void stage8(const dd::BeamArgs& a, uint32_t (&acc)[ND
     if (more) fill_stage(a, dlo_row, w_base, stride, c0 + 8, 8, nxt, lane, wave);
 #pragma unroll
     for (int i = 0; i < NDW; ++i) {
-        const int d = d_lo + wave + kWaves * i;
-        if (d < a.ndm) {
-            const cptr<uint32_t> trow = as_const(a.offs) + static_cast<int64_t>(d) * a.nchans;
-            accumulate_chunk<NL, G, 8, SECOND>(acc[i], pend[i], cur + 16 * lane, trow, c0);
+        // a trial past the last one (a short last DM block) repeats the last
+        // trial's offsets, so the code has no branch; its sums are never stored
+        const int d = min(d_lo + wave + kWaves * i, a.ndm - 1);
+        const cptr<uint32_t> trow = as_const(a.offs) + static_cast<int64_t>(d) * a.nchans;
+        accumulate_chunk<NL, G, 8, SECOND>(acc[i], pend[i], cur + 16 * lane, trow, c0);
+        // The trial's sums must exist here (an empty statement that reads and
+        // writes them): the compiler may not sink the adds past the next
+        // stage's barrier, where every trial's quads would be live at once.
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+#pragma unroll
+            for (int l = 0; l < NL; ++l) asm volatile("" : "+v"(acc[i][g][l]));
+            asm volatile("" : "+v"(pend[i][g]));
         }
     }
 }
@@ -389,8 +398,18 @@ __global__ __launch_bounds__(kThreads) void dedisperse_kernel(dd::BeamArgs a, in
 // item range [q*total/nq, (q+1)*total/nq)), so that the blocks of one XCD work
 // through neighbouring (beam, time tile, DM block) items.  Every block leaves
 // once its queue is drained.
+// The 12-level, 16-trial, one-group shape (the survey's) asks for 5 waves
+// per SIMD: the item queue's extra scalars would otherwise spill into enough
+// vector registers to leave 4 (the compiler then spills two per-item values
+// to scratch instead).
+template <int NL, int NDW, int G>
+constexpr int persistent_min_waves() {
+    return (NL == 12 && NDW == 4 && G == 1) ? 5 : 1;
+}
+
 template <int NL, int NDW, int G, bool OUT16>
-__global__ __launch_bounds__(kThreads) void dedisperse_persistent_kernel(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(persistent_min_waves<NL, NDW, G>())))
+void dedisperse_persistent_kernel(
     const dd::BeamArgs* __restrict__ beams, int nbeams, int64_t total, int stage_chans,
     unsigned long long* __restrict__ counters, int nq) {
     extern __shared__ uint4 lds[];
