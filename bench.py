@@ -216,6 +216,7 @@ def main():
     ap.add_argument("--no-small", action="store_true", help="skip the 256-channel small case")
     ap.add_argument("--no-multibeam", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-triage", action="store_true", help="skip the triage network leg")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the baseline-removal, clustering, subband and coincidence-mask legs")
     ap.add_argument("--serve-chunks", type=int, default=32,
@@ -384,7 +385,8 @@ def main():
         if nx:
             rec.update(nx)
         rec["rfi_mask"] = leg("13-beam coincidence mask", 15, lambda: bench_rfi_mask(args))
-    rec["triage"] = leg("triage network, 256 tiles", 20, lambda: bench_triage(args))
+    if not args.no_triage:
+        rec["triage"] = leg("triage network, 256 tiles", 20, lambda: bench_triage(args))
     legs["total"] = round(time.perf_counter() - T_START, 1)
     print(json.dumps(rec), flush=True)
 
