@@ -143,15 +143,22 @@ def test_all_threes_maximum_sums():
     of the 12- and 16-level counters and of uint16 at 21844 channels)."""
     torch = torch_dev()
     from paper_1112_0065_amd import _lib as L
-    for nchans, nsamps in [(1364, 700), (21844, 300)]:
+    # 1364 / 21844: the largest sums of the two counters (4-channel last
+    # chunk); 1360 / 21840: the same near the limit through 8-channel stages
+    # (an odd number of them: 170 is even, 2730 is even; 1352 gives 169)
+    for nchans, nsamps, tiles in [(1364, 700, [(4, 1, 16)]), (21844, 300, [(4, 1, 16)]),
+                                  (1352, 700, [(16, 1, 8), (4, 1, 8)]),
+                                  (1360, 700, [(16, 1, 8)]), (21840, 300, [(16, 1, 8)])]:
         dms = [0.0, 0.5]
         df = -0.01
         lv = np.full((nsamps, nchans), 3, np.uint8)
         fb = synth.make_tiny(0, nchans, nsamps, dms, df=df, levels=lv)
         p = L.dedisp_plan_create(nchans, fb.f_top, df, fb.tsamp, dms)
         for dtype in (torch.int16, torch.int32):
-            got = _run(p, fb.packed, nsamps, dtype, (4, 1, 16))
-            assert (got == 3 * nchans).all()
+            for tile in tiles:
+                log("all threes", nchans, dtype, tile)
+                got = _run(p, fb.packed, nsamps, dtype, tile)
+                assert (got == 3 * nchans).all(), (nchans, dtype, tile)
 
 
 def test_too_few_samples_and_bad_args():
