@@ -29,11 +29,11 @@ constexpr char kMagic[8] = {'T', 'R', 'I', 'A', 'G', 'E', '0', '1'};
 
 void free_acts(tk::Net& n) {
     void* ptrs[] = {n.a[0], n.a[1], n.a[2], n.a[3], n.p[0], n.p[1], n.p[2], n.p[3], n.idx[0], n.idx[1],
-                    n.idx[2], n.idx[3], n.g, n.logits, n.dlogit, n.dp, n.dz, n.part, n.scores};
+                    n.idx[2], n.idx[3], n.g, n.logits, n.dlogit, n.dp, n.dz, n.part, n.red, n.scores};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (int l = 0; l < 4; ++l) n.a[l] = n.p[l] = nullptr, n.idx[l] = nullptr;
-    n.g = n.logits = n.dlogit = n.dp = n.part = n.scores = nullptr;
+    n.g = n.logits = n.dlogit = n.dp = n.part = n.red = n.scores = nullptr;
     n.dz = nullptr;
     n.cap = 0;
 }
@@ -60,6 +60,7 @@ hipError_t ensure_cap(tk::Net& n, int cap) {
     if (e == hipSuccess) e = hipMalloc(&n.dp, N * 32 * 128 * tk::kCH * 4);
     if (e == hipSuccess) e = hipMalloc(&n.dz, N * 64 * 256 * tk::kCH * 2);
     if (e == hipSuccess) e = hipMalloc(&n.part, parts * 4);
+    if (e == hipSuccess) e = hipMalloc(&n.red, static_cast<size_t>(tk::kRedSlices) * 9 * tk::kCH * tk::kCH * 4);
     if (e == hipSuccess) n.cap = cap;
     return e;
 }

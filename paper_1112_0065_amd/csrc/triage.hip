@@ -290,21 +290,45 @@ __global__ void gap_bwd_kernel(const float* __restrict__ dlogit, const float* __
 }
 
 // Max-pool backward + ReLU mask, rounded to bf16: dz = bf16(dA * (a > 0)).
-__global__ void pool_relu_bwd_kernel(const float* __restrict__ dp, const uint8_t* __restrict__ idx,
-                                     const uint16_t* __restrict__ a, int N, int H, int W,
-                                     uint16_t* __restrict__ dz) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t total = static_cast<int64_t>(N) * H * W * kCH;
-    if (i >= total) return;
-    const int c = static_cast<int>(i % kCH);
-    const int x = static_cast<int>((i / kCH) % W);
-    const int y = static_cast<int>((i / (kCH * W)) % H);
-    const int64_t n = i / (static_cast<int64_t>(kCH) * W * H);
-    const int64_t pi = ((n * (H / 2) + y / 2) * (W / 2) + x / 2) * kCH + c;
-    const int k = ((y & 1) << 1) | (x & 1);
-    float v = (idx[pi] == k) ? dp[pi] : 0.0f;
-    if (!(bf2f(a[i]) > 0.0f)) v = 0.0f;
-    dz[i] = f2bf(v);
+// One thread per (pixel, group of 8 channels): 16-byte loads and stores of
+// the activations and gradients, the block's image row from its index (the
+// divisions are per block, in scalar registers).
+__global__ __launch_bounds__(256) void pool_relu_bwd_kernel(const float* __restrict__ dp,
+                                                            const uint8_t* __restrict__ idx,
+                                                            const uint16_t* __restrict__ a, int N,
+                                                            int H, int W, uint16_t* __restrict__ dz) {
+    const int bpr = (4 * W + 255) / 256;   // blocks per image row
+    const int64_t row = blockIdx.x / bpr;  // n * H + y
+    if (row >= static_cast<int64_t>(N) * H) return;
+    const int j = static_cast<int>(blockIdx.x % bpr) * 256 + static_cast<int>(threadIdx.x);
+    if (j >= 4 * W) return;
+    const int x = j >> 2, c0 = 8 * (j & 3);
+    const int y = static_cast<int>(row % H);
+    const int64_t n = row / H;
+    const int64_t i = (row * W + x) * kCH + c0;
+    const int64_t pi = ((n * (H / 2) + y / 2) * (W / 2) + x / 2) * kCH + c0;
+    const uint8_t k = static_cast<uint8_t>(((y & 1) << 1) | (x & 1));
+    const uint2 iw = *reinterpret_cast<const uint2*>(idx + pi);
+    const float4 d0 = *reinterpret_cast<const float4*>(dp + pi);
+    const float4 d1 = *reinterpret_cast<const float4*>(dp + pi + 4);
+    const uint4 av = *reinterpret_cast<const uint4*>(a + i);
+    const float dv[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+    const uint32_t aw[4] = {av.x, av.y, av.z, av.w};
+    uint32_t ow[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = 2 * q + h;
+            const uint8_t win = static_cast<uint8_t>(((c < 4 ? iw.x : iw.y) >> (8 * (c & 3))) & 0xFFu);
+            float v = win == k ? dv[c] : 0.0f;
+            if (!(bf2f(static_cast<uint16_t>(aw[q] >> (16 * h))) > 0.0f)) v = 0.0f;
+            w |= static_cast<uint32_t>(f2bf(v)) << (16 * h);
+        }
+        ow[q] = w;
+    }
+    *reinterpret_cast<uint4*>(dz + i) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
 }
 
 // Weight gradient of a 32 -> 32 layer for one tap, over `rows` consecutive
@@ -373,47 +397,111 @@ __global__ __launch_bounds__(64) void wgrad32_mfma_kernel(const uint16_t* __rest
                 dst[(16 * rt + 4 * kq + j) * kCH + 16 * ct + idx16] = acc[rt][ct][j];
 }
 
-// Layer-1 weight gradient (Cin = 1) and every layer's bias gradient partials:
-// block = `rows` image rows; part[blk][k] over k < 288 (+32 bias) for layer 1,
-// or part[blk][co] (bias only) otherwise.
-__global__ __launch_bounds__(320) void wgrad1_bias_kernel(const uint16_t* __restrict__ x,
-                                                          const uint16_t* __restrict__ dz, int N, int H,
-                                                          int W, int rows, int with_w,
-                                                          float* __restrict__ part, int stride) {
-    const int k = threadIdx.x;   // < 288: weight (co = k / 9, tap = k % 9); 288..319: bias of co = k - 288
+// Layer-1 (Cin = 1) weight and bias gradient partials on MFMA over `rows`
+// image rows per block: M = co, N = the 9 taps and a column of ones (the bias;
+// columns 10-15 are zero), K = pixels (32 per step).  Writes part[blk][co * 9 +
+// tap] (288 values) and part[blk][288 + co].
+__global__ __launch_bounds__(64) void wgrad1_mfma_kernel(const uint16_t* __restrict__ x,
+                                                         const uint16_t* __restrict__ dz, int N,
+                                                         int H, int W, int rows,
+                                                         float* __restrict__ part) {
+    const int lane = threadIdx.x;
+    const int idx16 = lane & 15;
+    const int kq = lane >> 4;
+    const int col = idx16;   // B column: tap (< 9), bias (9), zero (> 9)
+    const int ky = col / 3 - 1, kx = col % 3 - 1;
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rows;
     const int64_t nrows = static_cast<int64_t>(N) * H;
-    float s = 0.0f;
-    if (k < 288 && with_w) {
-        const int co = k / 9, tap = k % 9;
-        const int ky = tap / 3 - 1, kx = tap % 3 - 1;
-        for (int64_t rr = r0; rr < min(r0 + rows, nrows); ++rr) {
-            const int y = static_cast<int>(rr % H);
-            const int64_t n = rr / H;
-            const int y2 = y + ky;
-            if (y2 < 0 || y2 >= H) continue;
-            for (int xx = 0; xx < W; ++xx) {
-                const int x2 = xx + kx;
-                if (x2 < 0 || x2 >= W) continue;
-                s += bf2f(dz[((n * H + y) * W + xx) * kCH + co]) * bf2f(x[(n * H + y2) * W + x2]);
+    constexpr uint16_t kOne = 0x3F80;   // bf16 1.0
+    f32x4 acc[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t rr = r0; rr < min(r0 + rows, nrows); ++rr) {
+        const int y = static_cast<int>(rr % H);
+        const int64_t n = rr / H;
+        const int y2 = y + ky;
+        const bool yok = col < 9 && y2 >= 0 && y2 < H;
+        for (int x0 = 0; x0 < W; x0 += 32) {
+            bf16x8 afr[2];
+            // A[co][k = pixel]: 8 consecutive pixels of one output channel
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) {
+                const int co = 16 * rt + idx16;
+                uint16_t v[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = dz[((n * H + y) * W + x0 + 8 * kq + j) * kCH + co];
+                afr[rt] = pack8(v);
             }
+            // B[k = pixel][col]: the input shifted by the tap, or ones
+            uint16_t v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int x2 = x0 + 8 * kq + j + kx;
+                const bool ok = yok && x2 >= 0 && x2 < W;
+                v[j] = ok ? x[(n * H + y2) * W + x2] : (col == 9 ? kOne : uint16_t(0));
+            }
+            const bf16x8 bfr = pack8(v);
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+                acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[rt], bfr, acc[rt], 0, 0, 0);
         }
-        part[static_cast<int64_t>(blockIdx.x) * stride + k] = s;
-    } else if (k >= 288) {
-        const int co = k - 288;
-        for (int64_t rr = r0; rr < min(r0 + rows, nrows); ++rr)
-            for (int xx = 0; xx < W; ++xx) s += bf2f(dz[(rr * W + xx) * kCH + co]);
-        part[static_cast<int64_t>(blockIdx.x) * stride + (with_w ? 288 : 0) + co] = s;
+    }
+    // D[co][col]: lane holds co = 16 rt + 4 kq + j, column idx16
+    float* dst = part + static_cast<int64_t>(blockIdx.x) * 320;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int co = 16 * rt + 4 * kq + j;
+            if (col < 9)
+                dst[co * 9 + col] = acc[rt][j];
+            else if (col == 9)
+                dst[288 + co] = acc[rt][j];
+        }
+}
+
+// Bias gradient partials of a 32-channel layer over `rows` image rows per
+// block: part[blk][co] = sum of dz[p][co] over the block's pixels, in 8 slices
+// of pixels (32 consecutive channels per slice and pixel: coalesced), then the
+// slices in order.
+__global__ __launch_bounds__(256) void bias_parts_kernel(const uint16_t* __restrict__ dz, int N, int H,
+                                                         int W, int rows, float* __restrict__ part) {
+    __shared__ float sl[8][kCH];
+    const int co = threadIdx.x & (kCH - 1), q = threadIdx.x >> 5;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rows;
+    const int64_t nrows = static_cast<int64_t>(N) * H;
+    const int64_t p0 = r0 * W, p1 = min(r0 + rows, nrows) * W;
+    float acc = 0.0f;
+    for (int64_t p = p0 + q; p < p1; p += 8) acc += bf2f(dz[p * kCH + co]);
+    sl[q][co] = acc;
+    __syncthreads();
+    if (threadIdx.x < kCH) {
+        float t = 0.0f;
+        for (int k = 0; k < 8; ++k) t += sl[k][threadIdx.x];
+        part[static_cast<int64_t>(blockIdx.x) * kCH + threadIdx.x] = t;
     }
 }
 
-// out[i] = sum over blocks b (in order) of part[b * stride + i], i < n.
-__global__ void reduce_parts_kernel(const float* __restrict__ part, int nparts, int stride, int n,
-                                    float* __restrict__ out) {
+// out[i] = sum over the parts b of part[b * stride + i], i < n, in a fixed
+// order: slice s of kRedSlices adds its contiguous range of parts in order
+// (first kernel, one thread per (i, s)), then the slices are added in order.
+__global__ void reduce_slices_kernel(const float* __restrict__ part, int nparts, int stride, int n,
+                                     float* __restrict__ red) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int sl = blockIdx.y;
+    if (i >= n) return;
+    const int b0 = static_cast<int>(static_cast<int64_t>(nparts) * sl / kRedSlices);
+    const int b1 = static_cast<int>(static_cast<int64_t>(nparts) * (sl + 1) / kRedSlices);
+    float s = 0.0f;
+    for (int b = b0; b < b1; ++b) s += part[static_cast<int64_t>(b) * stride + i];
+    red[static_cast<int64_t>(sl) * n + i] = s;
+}
+
+__global__ void reduce_final_kernel(const float* __restrict__ red, int n, float* __restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     float s = 0.0f;
-    for (int b = 0; b < nparts; ++b) s += part[static_cast<int64_t>(b) * stride + i];
+    for (int k = 0; k < kRedSlices; ++k) s += red[static_cast<int64_t>(k) * n + i];
     out[i] = s;
 }
 
@@ -510,6 +598,15 @@ hipError_t launch_forward(const Net& net, const uint16_t* tiles, int N, hipStrea
     return hipGetLastError();
 }
 
+// Sum of per-block partials in a fixed order (two kernels; `red` holds
+// kRedSlices x n floats).
+static void launch_reduce(const float* part, int nparts, int stride, int n, float* red, float* out,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(reduce_slices_kernel, dim3(blocks(n, 64), kRedSlices), dim3(64), 0, s, part, nparts,
+                       stride, n, red);
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(blocks(n, 256)), dim3(256), 0, s, red, n, out);
+}
+
 hipError_t launch_backward(const Net& net, const uint16_t* tiles, const float* labels, int N,
                            hipStream_t s) {
     hipLaunchKernelGGL(bce_kernel, dim3(1), dim3(256), 0, s, net.logits, labels, N, net.dlogit, net.loss);
@@ -520,31 +617,26 @@ hipError_t launch_backward(const Net& net, const uint16_t* tiles, const float* l
     const int Hs[4] = {64, 32, 16, 8}, Ws[4] = {256, 128, 64, 32};
     for (int l = 3; l >= 0; --l) {
         const int H = Hs[l], W = Ws[l];
-        const int64_t ne = static_cast<int64_t>(N) * H * W * kCH;
-        hipLaunchKernelGGL(pool_relu_bwd_kernel, dim3(blocks(ne, 256)), dim3(256), 0, s, net.dp, net.idx[l],
-                           net.a[l], N, H, W, net.dz);
+        const int64_t nblk = static_cast<int64_t>(N) * H * ((4 * W + 255) / 256);
+        hipLaunchKernelGGL(pool_relu_bwd_kernel, dim3(static_cast<unsigned>(nblk)), dim3(256), 0, s, net.dp,
+                           net.idx[l], net.a[l], N, H, W, net.dz);
         const int64_t nrows = static_cast<int64_t>(N) * H;
         const int rows = kRowsPerBlock;
         const int nparts = static_cast<int>((nrows + rows - 1) / rows);
         const uint16_t* xin = l == 0 ? tiles : net.p[l - 1];
         if (l == 0) {
-            hipLaunchKernelGGL(wgrad1_bias_kernel, dim3(nparts), dim3(320), 0, s, xin, net.dz, N, H, W, rows, 1,
-                               net.part, 320);
-            hipLaunchKernelGGL(reduce_parts_kernel, dim3(blocks(288, 256)), dim3(256), 0, s, net.part, nparts,
-                               320, 288, net.grad + net.off.w[0]);
-            hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(64), 0, s, net.part + 288, nparts, 320, kCH,
-                               net.grad + net.off.b[0]);
+            hipLaunchKernelGGL(wgrad1_mfma_kernel, dim3(nparts), dim3(64), 0, s, xin, net.dz, N, H, W, rows,
+                               net.part);
+            launch_reduce(net.part, nparts, 320, 288, net.red, net.grad + net.off.w[0], s);
+            launch_reduce(net.part + 288, nparts, 320, kCH, net.red, net.grad + net.off.b[0], s);
         } else {
             hipLaunchKernelGGL(wgrad32_mfma_kernel, dim3(nparts, 9), dim3(64), 0, s, xin, net.dz, N, H, W, rows,
                                net.part);
-            hipLaunchKernelGGL(reduce_parts_kernel, dim3(blocks(9 * kCH * kCH, 256)), dim3(256), 0, s, net.part,
-                               nparts, 9 * kCH * kCH, 9 * kCH * kCH, net.dtap);
+            launch_reduce(net.part, nparts, 9 * kCH * kCH, 9 * kCH * kCH, net.red, net.dtap, s);
             hipLaunchKernelGGL(wgrad_to_master_kernel, dim3(blocks(9 * kCH * kCH, 256)), dim3(256), 0, s,
                                net.dtap, net.grad + net.off.w[l]);
-            hipLaunchKernelGGL(wgrad1_bias_kernel, dim3(nparts), dim3(320), 0, s, xin, net.dz, N, H, W, rows, 0,
-                               net.part, kCH);
-            hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(64), 0, s, net.part, nparts, kCH, kCH,
-                               net.grad + net.off.b[l]);
+            hipLaunchKernelGGL(bias_parts_kernel, dim3(nparts), dim3(256), 0, s, net.dz, N, H, W, rows, net.part);
+            launch_reduce(net.part, nparts, kCH, kCH, net.red, net.grad + net.off.b[l], s);
             // input gradient -> d p_{l-1} (float32)
             const int64_t nb = static_cast<int64_t>(N) * H * (W / 32);
             hipLaunchKernelGGL(conv32_mfma_kernel<1>, dim3(static_cast<unsigned>(nb)), dim3(64), 0, s, net.dz, N, H,

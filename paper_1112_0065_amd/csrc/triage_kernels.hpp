@@ -12,6 +12,8 @@ namespace tk {
 
 constexpr int kCH = 32;
 constexpr int kRowsPerBlock = 8;
+// Slices of the fixed-order reduction of per-block gradient partials.
+constexpr int kRedSlices = 32;
 // w1 [32][1][3][3], b1, (w, b) x 3 layers of [32][32][3][3], wf [32], bf [1]
 constexpr int kNumParams = 32 * 9 + 32 + 3 * (32 * 32 * 9 + 32) + 32 + 1;
 
@@ -61,6 +63,7 @@ struct Net {
     float* dp;          // float32 gradient of the pooled map (largest layer)
     uint16_t* dz;       // bf16 gradient of the pre-activation (largest layer)
     float* part;        // per-block partial sums of weight / bias gradients
+    float* red;         // [kRedSlices][9 * 32 * 32] slices of their reduction
     float* dtap;        // [9][32][32]
     float* scores;      // [cap]
     int* bad;           // non-finite counter
