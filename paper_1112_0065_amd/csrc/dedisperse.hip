@@ -18,7 +18,9 @@
 //     table also carries the shift within the word), aligns the two words
 //     to the trial's delay with one funnel shift per plane, and adds the 32
 //     2-bit samples into a bit-sliced counter with carry-save adder trees:
-//     about 8 bit-operations add 32 samples (see gen_csa.py);
+//     8 channels at a time into a 5-level low counter (2 bit-operations per
+//     input plane, see gen_csa.py), whose carry-out plane waits for the next
+//     8 channels' so that the two ripple through the upper levels once;
 //   * after the last stage the counter planes are transposed to integers in
 //     registers and written once (int32 or uint16).
 // The result is exact; its order of additions is irrelevant (integers).
