@@ -91,21 +91,23 @@ __global__ __launch_bounds__(256) void tiles_kernel(const uint16_t* __restrict__
 // ---------------------------------------------------------------------------
 // Layer 1: 1 -> 32 channels, 3x3, pad 1, + bias, ReLU; VALU.
 // ---------------------------------------------------------------------------
+// The weights and biases are read through the constant address space, so
+// they load into scalar registers (uniform over the block) and every
+// multiply-add takes its weight as a scalar operand.
 __global__ __launch_bounds__(256) void conv1_fwd_kernel(const uint16_t* __restrict__ x, int N,
                                                         const uint16_t* __restrict__ w1b,
                                                         const float* __restrict__ b1,
                                                         uint16_t* __restrict__ a) {
-    __shared__ float ws[kCH * 9];
-    __shared__ float bs[kCH];
-    for (int i = threadIdx.x; i < kCH * 9; i += blockDim.x) ws[i] = bf2f(w1b[i]);
-    if (threadIdx.x < kCH) bs[threadIdx.x] = b1[threadIdx.x];
-    __syncthreads();
+    typedef const __attribute__((address_space(4))) uint16_t* cw_t;
+    typedef const __attribute__((address_space(4))) float* cb_t;
+    const cw_t wc = (cw_t)w1b;
+    const cb_t bc = (cb_t)b1;
     const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t npix = static_cast<int64_t>(N) * 64 * 256;
     if (p >= npix) return;
-    const int xx = static_cast<int>(p % 256);
-    const int yy = static_cast<int>((p / 256) % 64);
-    const int64_t n = p / (64 * 256);
+    const int xx = static_cast<int>(p & 255);
+    const int yy = static_cast<int>((p >> 8) & 63);
+    const int64_t n = p >> 14;
     float in[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
@@ -115,11 +117,11 @@ __global__ __launch_bounds__(256) void conv1_fwd_kernel(const uint16_t* __restri
     uint32_t packed[kCH / 2];
 #pragma unroll
     for (int c = 0; c < kCH; c += 2) {
-        float z0 = bs[c], z1 = bs[c + 1];
+        float z0 = bc[c], z1 = bc[c + 1];
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
-            z0 += ws[c * 9 + t] * in[t];
-            z1 += ws[(c + 1) * 9 + t] * in[t];
+            z0 += bf2f(wc[c * 9 + t]) * in[t];
+            z1 += bf2f(wc[(c + 1) * 9 + t]) * in[t];
         }
         packed[c / 2] = static_cast<uint32_t>(f2bf(fmaxf(z0, 0.0f))) |
                         (static_cast<uint32_t>(f2bf(fmaxf(z1, 0.0f))) << 16);
@@ -199,49 +201,86 @@ __global__ __launch_bounds__(64) void conv32_mfma_kernel(const uint16_t* __restr
 // ---------------------------------------------------------------------------
 // 2x2 max-pool (first maximum in raster order) with the winner's index.
 // ---------------------------------------------------------------------------
-__global__ void maxpool_fwd_kernel(const uint16_t* __restrict__ a, int N, int H, int W,
-                                   uint16_t* __restrict__ p, uint8_t* __restrict__ idx) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+// One thread per (pooled pixel, group of 8 channels): four 16-byte loads of
+// the window, one 16-byte store of the maxima and one 8-byte store of the
+// winners (the first of equal maxima); the block's pooled row from its index.
+__global__ __launch_bounds__(256) void maxpool_fwd_kernel(const uint16_t* __restrict__ a, int N, int H,
+                                                          int W, uint16_t* __restrict__ p,
+                                                          uint8_t* __restrict__ idx) {
     const int H2 = H / 2, W2 = W / 2;
-    const int64_t total = static_cast<int64_t>(N) * H2 * W2 * kCH;
-    if (i >= total) return;
-    const int c = static_cast<int>(i % kCH);
-    const int x2 = static_cast<int>((i / kCH) % W2);
-    const int y2 = static_cast<int>((i / (kCH * W2)) % H2);
-    const int64_t n = i / (static_cast<int64_t>(kCH) * W2 * H2);
-    float best = -1.0f;
-    int bi = 0;
-    uint16_t bv = 0;
+    const int bpr = (4 * W2 + 255) / 256;   // blocks per pooled row
+    const int64_t row = blockIdx.x / bpr;   // n * H2 + y2
+    if (row >= static_cast<int64_t>(N) * H2) return;
+    const int j = static_cast<int>(blockIdx.x % bpr) * 256 + static_cast<int>(threadIdx.x);
+    if (j >= 4 * W2) return;
+    const int x2 = j >> 2, c0 = 8 * (j & 3);
+    const int y2 = static_cast<int>(row % H2);
+    const int64_t n = row / H2;
+    uint4 win[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int y = 2 * y2 + (k >> 1), x = 2 * x2 + (k & 1);
-        const uint16_t v = a[((n * H + y) * W + x) * kCH + c];
-        const float f = bf2f(v);
-        if (k == 0 || f > best) {
-            best = f;
-            bi = k;
-            bv = v;
-        }
+        win[k] = *reinterpret_cast<const uint4*>(a + ((n * H + y) * W + x) * kCH + c0);
     }
-    p[i] = bv;
-    idx[i] = static_cast<uint8_t>(bi);
+    uint32_t ow[4];
+    uint32_t iw[2] = {0u, 0u};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = 2 * q + h;
+            float best = -1.0f;
+            uint32_t bi = 0, bv = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t word = q == 0 ? win[k].x : q == 1 ? win[k].y : q == 2 ? win[k].z : win[k].w;
+                const uint32_t v = (word >> (16 * h)) & 0xFFFFu;
+                const float f = bf2f(static_cast<uint16_t>(v));
+                if (k == 0 || f > best) {
+                    best = f;
+                    bi = static_cast<uint32_t>(k);
+                    bv = v;
+                }
+            }
+            w |= bv << (16 * h);
+            iw[c >> 2] |= bi << (8 * (c & 3));
+        }
+        ow[q] = w;
+    }
+    const int64_t o = (row * W2 + x2) * kCH + c0;
+    *reinterpret_cast<uint4*>(p + o) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+    *reinterpret_cast<uint2*>(idx + o) = make_uint2(iw[0], iw[1]);
 }
 
-// Global average over the 4x16 map, then the 32 -> 1 linear layer.
-__global__ void gap_fc_fwd_kernel(const uint16_t* __restrict__ p4, int N, const float* __restrict__ wf,
-                                  const float* __restrict__ bf, float* __restrict__ g,
-                                  float* __restrict__ logits) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+// Global average over the 4x16 map, then the 32 -> 1 linear layer: one block
+// of 64 threads per tile, thread (half, channel) summing 32 of the 64
+// positions (consecutive channels: coalesced), then the halves and the
+// channels' products in a fixed order.
+__global__ __launch_bounds__(64) void gap_fc_fwd_kernel(const uint16_t* __restrict__ p4, int N,
+                                                        const float* __restrict__ wf,
+                                                        const float* __restrict__ bf, float* __restrict__ g,
+                                                        float* __restrict__ logits) {
+    __shared__ float hs[2][kCH];
+    __shared__ float prod[kCH];
+    const int n = blockIdx.x;
     if (n >= N) return;
-    float lg = bf[0];
-    for (int c = 0; c < kCH; ++c) {
-        float s = 0.0f;
-        for (int q = 0; q < 64; ++q) s += bf2f(p4[(static_cast<int64_t>(n) * 64 + q) * kCH + c]);
-        s *= (1.0f / 64.0f);
-        g[n * kCH + c] = s;
-        lg += s * wf[c];
+    const int c = threadIdx.x & (kCH - 1), h = threadIdx.x >> 5;
+    float s = 0.0f;
+    for (int q = 32 * h; q < 32 * h + 32; ++q) s += bf2f(p4[(static_cast<int64_t>(n) * 64 + q) * kCH + c]);
+    hs[h][c] = s;
+    __syncthreads();
+    if (threadIdx.x < kCH) {
+        const float gc = (hs[0][c] + hs[1][c]) * (1.0f / 64.0f);
+        g[n * kCH + c] = gc;
+        prod[c] = gc * wf[c];
     }
-    logits[n] = lg;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float lg = bf[0];
+        for (int k = 0; k < kCH; ++k) lg += prod[k];
+        logits[n] = lg;
+    }
 }
 
 // Loss (mean binary cross-entropy with logits) and d loss / d logit; one block.
@@ -264,19 +303,28 @@ __global__ __launch_bounds__(256) void bce_kernel(const float* __restrict__ logi
     if (threadIdx.x == 0) *loss = part[0] / static_cast<float>(N);
 }
 
-// Linear + average backward: gradients of wf, bf; d p4 (float32).
-__global__ void fc_bwd_kernel(const float* __restrict__ dlogit, const float* __restrict__ g, int N,
-                              const float* __restrict__ wf, float* __restrict__ gwf,
-                              float* __restrict__ gbf) {
-    const int c = threadIdx.x;
-    if (c < kCH) {
+// Linear + average backward: gradients of wf, bf.  One block: thread
+// (slice, channel) sums the tiles of its slice (every 8th), the 33rd column
+// being the bias, then the 8 slices in order.
+__global__ __launch_bounds__(512) void fc_bwd_kernel(const float* __restrict__ dlogit,
+                                                     const float* __restrict__ g, int N,
+                                                     const float* __restrict__ wf, float* __restrict__ gwf,
+                                                     float* __restrict__ gbf) {
+    __shared__ float sl[8][kCH + 1];
+    const int c = threadIdx.x % 64, q = threadIdx.x / 64;   // c < 33 used
+    if (c <= kCH) {
         float s = 0.0f;
-        for (int n = 0; n < N; ++n) s += dlogit[n] * g[n * kCH + c];
-        gwf[c] = s;
-    } else if (c == kCH) {
+        for (int n = q; n < N; n += 8) s += dlogit[n] * (c < kCH ? g[n * kCH + c] : 1.0f);
+        sl[q][c] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x <= kCH) {
         float s = 0.0f;
-        for (int n = 0; n < N; ++n) s += dlogit[n];
-        gbf[0] = s;
+        for (int k = 0; k < 8; ++k) s += sl[k][threadIdx.x];
+        if (threadIdx.x < kCH)
+            gwf[threadIdx.x] = s;
+        else
+            gbf[0] = s;
     }
 }
 
@@ -587,13 +635,13 @@ hipError_t launch_forward(const Net& net, const uint16_t* tiles, int N, hipStrea
                                net.p[l - 1], N, H, W, net.wfwd + (l - 1) * kCH * 9 * kCH,
                                net.master + net.off.b[l], static_cast<void*>(net.a[l]));
         }
-        const int64_t np = static_cast<int64_t>(N) * (H / 2) * (W / 2) * kCH;
-        hipLaunchKernelGGL(maxpool_fwd_kernel, dim3(blocks(np, 256)), dim3(256), 0, s, net.a[l], N, H, W,
-                           net.p[l], net.idx[l]);
+        const int64_t nbp = static_cast<int64_t>(N) * (H / 2) * ((4 * (W / 2) + 255) / 256);
+        hipLaunchKernelGGL(maxpool_fwd_kernel, dim3(static_cast<unsigned>(nbp)), dim3(256), 0, s, net.a[l], N, H,
+                           W, net.p[l], net.idx[l]);
         H /= 2;
         W /= 2;
     }
-    hipLaunchKernelGGL(gap_fc_fwd_kernel, dim3(blocks(N, 64)), dim3(64), 0, s, net.p[3], N,
+    hipLaunchKernelGGL(gap_fc_fwd_kernel, dim3(N), dim3(64), 0, s, net.p[3], N,
                        net.master + net.off.wf, net.master + net.off.bf, net.g, net.logits);
     return hipGetLastError();
 }
@@ -610,7 +658,7 @@ static void launch_reduce(const float* part, int nparts, int stride, int n, floa
 hipError_t launch_backward(const Net& net, const uint16_t* tiles, const float* labels, int N,
                            hipStream_t s) {
     hipLaunchKernelGGL(bce_kernel, dim3(1), dim3(256), 0, s, net.logits, labels, N, net.dlogit, net.loss);
-    hipLaunchKernelGGL(fc_bwd_kernel, dim3(1), dim3(64), 0, s, net.dlogit, net.g, N, net.master + net.off.wf,
+    hipLaunchKernelGGL(fc_bwd_kernel, dim3(1), dim3(512), 0, s, net.dlogit, net.g, N, net.master + net.off.wf,
                        net.grad + net.off.wf, net.grad + net.off.bf);
     hipLaunchKernelGGL(gap_bwd_kernel, dim3(blocks(static_cast<int64_t>(N) * 64 * kCH, 256)), dim3(256), 0,
                        s, net.dlogit, net.master + net.off.wf, N, net.dp);
