@@ -37,7 +37,9 @@ constexpr int kS2Threads = 256;
 constexpr int kS2Tile = 1024;        // output samples per block (4 per thread)
 constexpr int kS2PerThread = kS2Tile / kS2Threads;
 constexpr int kMaxGroup = 16;        // fine trials per coarse trial
-constexpr int kS2LdsBytes = 64 * 1024;
+// LDS per block: rows of a few subbands at a time; 16 KiB (several blocks per
+// CU) ran stage 2 a fifth faster than 64 KiB, 8-12 KiB no faster
+constexpr int kS2LdsBytes = 16 * 1024;
 
 // Block (tile, group q): out[d][t] for the group's trials and t in the tile.
 // sub: uint16 series of subband s at sub + ncoarse * (s * nsamps - cum[s]),
