@@ -242,7 +242,10 @@ __global__ __launch_bounds__(kThreads) void baseline_kernel(const T* __restrict_
                                                             int offset, int64_t nseg, uint64_t magic,
                                                             int shift, U* __restrict__ out) {
     const int lane = threadIdx.x & 63;
-    const int64_t item = (static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x) >> 6;
+    // the wave's item, in scalar registers (so is everything derived from
+    // it, the row's buffer resource included: the loads need it uniform)
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int64_t item = static_cast<int64_t>(blockIdx.x) * (kThreads / 64) + wave;
     if (item >= static_cast<int64_t>(ndm) * nseg) return;   // whole waves
     const int d = static_cast<int>(item / nseg);
     const int64_t t0 = (item % nseg) * kBlSeg;
