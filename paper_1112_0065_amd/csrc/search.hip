@@ -207,7 +207,7 @@ __global__ __launch_bounds__(kThreads) void boxcar_kernel(const T* __restrict__ 
 // multiply-shift below.  The loads of the next step are in flight while a
 // step is computed.
 constexpr int kBlSeg = 16384;       // outputs per wave
-constexpr int kBlRows = 8;          // rows of 64 outputs per step
+constexpr int kBlRows = 16;         // rows of 64 outputs per step
 constexpr int kBlStep = 64 * kBlRows;
 
 // Inclusive prefix sum over the 64 lanes of a wave: shifts within each row
