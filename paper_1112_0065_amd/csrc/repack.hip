@@ -49,13 +49,24 @@ __global__ __launch_bounds__(256) void repack_2bit_kernel(const uint8_t* __restr
                                                           uint2* __restrict__ words,
                                                           int64_t nwords, int64_t ntiles, int vec16,
                                                           int st16, const uint8_t* __restrict__ mask,
-                                                          int64_t mask_n) {
+                                                          int64_t mask_n, int ncx) {
     // the input tile, then (after every wave holds its words) the output tile
     __shared__ uint32_t buf[kBufWords];
     const int tid = threadIdx.x;
-    const int c0 = blockIdx.x * kTileC;          // channel tiles vary fastest: the blocks
-    const int row_bytes = nchans >> 2;           // of one row run together
-    for (int64_t tile = blockIdx.y; tile < ntiles; tile += gridDim.y) {
+    // Blocks are dealt to the 8 XCDs in turn (block b to XCD b % 8).  Renumber
+    // them so that each XCD takes one contiguous run of (tile, channel tile)
+    // items: the channel tiles of a sample range, which share the 128-byte
+    // lines of the input rows, then read them through one L2.
+    const int nb = static_cast<int>(gridDim.x);
+    const int b = static_cast<int>(blockIdx.x);
+    const int per = nb >> 3;
+    const int rem = nb & 7;
+    const int xcd = b & 7;
+    const int item = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + (b >> 3);
+    const int c0 = (item % ncx) * kTileC;
+    const int64_t tile = item / ncx;
+    const int row_bytes = nchans >> 2;
+    if (tile >= ntiles) return;
     const int64_t t0 = tile * kTileT;
 
     // 1. 512 rows x 64 bytes: thread -> (row, 16-byte chunk), 8 chunks each
@@ -135,8 +146,6 @@ __global__ __launch_bounds__(256) void repack_2bit_kernel(const uint8_t* __restr
             dst[1] = make_uint2(src[2], src[3]);
         }
     }
-    __syncthreads();   // the buffer is refilled by the next tile
-    }
 }
 
 }  // namespace
@@ -149,12 +158,14 @@ hipError_t launch_repack(const uint8_t* in, int64_t nsamps, int nchans, uint2* w
                          int64_t nwords, hipStream_t s, const uint8_t* mask, int64_t mask_n) {
     if (nwords != repack_words(nsamps) || nwords % 2) return hipErrorInvalidValue;
     const int64_t tiles_t = (nwords + kTileW - 1) / kTileW;
-    const dim3 grid(static_cast<unsigned>((nchans + kTileC - 1) / kTileC),
-                    static_cast<unsigned>(std::min<int64_t>(tiles_t, 65535)));
+    const int ncx = (nchans + kTileC - 1) / kTileC;
+    const int64_t nblocks = tiles_t * ncx;    // one block per (tile, channel tile)
+    if (nblocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    const dim3 grid(static_cast<unsigned>(nblocks));
     const int vec16 = ((nchans >> 2) % 16 == 0) && (reinterpret_cast<uintptr_t>(in) % 16 == 0);
     const int st16 = reinterpret_cast<uintptr_t>(words) % 16 == 0;
     hipLaunchKernelGGL(repack_2bit_kernel, grid, dim3(256), 0, s, in, nsamps, nchans, words,
-                       nwords, tiles_t, vec16, st16, mask, mask ? mask_n : 0);
+                       nwords, tiles_t, vec16, st16, mask, mask ? mask_n : 0, ncx);
     return hipGetLastError();
 }
 
