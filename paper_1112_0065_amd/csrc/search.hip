@@ -22,6 +22,7 @@
 // those with events are written: both passes work through lists of them.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "dedisp_internal.hpp"
 #include "intmath.hpp"
@@ -112,9 +113,11 @@ __device__ void load_prefix(const T* __restrict__ row, int64_t nout, int64_t fir
     if (vmax) {
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) m = max(m, static_cast<uint32_t>(__shfl_xor(m, o, 64)));
-        if ((threadIdx.x & 63) == 0) atomicMax(vmax, m);
     }
     __syncthreads();
+    // after the barrier, which orders them after the caller's clearing of
+    // *vmax; the barrier at the end orders them before its readers
+    if (vmax && (threadIdx.x & 63) == 0) atomicMax(vmax, m);
     // each thread scans a contiguous chunk (odd chunk stride: no bank conflicts)
     const int chunk = (((n - 1) + kThreads - 1) / kThreads) | 1;
     const int lo = 1 + threadIdx.x * chunk;
@@ -220,6 +223,87 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x142, 0xA, 0xF, false));
     x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x143, 0xC, 0xF, false));
     return x;
+}
+
+// The same running sums of a uint16 series window, for rows of a multiple of
+// 4 samples from an 8-byte aligned series, without the LDS passes of the
+// scan.  The window is read from a = first rounded down to a multiple of 4
+// (and not below 0) in kRounds rounds of 1024 samples; in round i thread t
+// takes samples a + 4(256 i + t) .. + 3 with one 8-byte load (every load lies
+// wholly inside the row or wholly past its end, where it reads 0).  The
+// thread sums its four, a DPP scan per round gives the wave's prefix, one
+// exchange of the wave totals of every round gives the block's, and each
+// group of four running sums goes to LDS with one 16-byte store.  The samples
+// between a and first and past the window enter the sums too: only
+// differences of the running sums are used, and the largest value only gates
+// the fast path, so both stay exact.  lds needs kRunWords words.
+// Returns ps with ps[i] - ps[j] = the sum of s[first + j .. first + i).
+constexpr int kRounds = 9;
+constexpr int kRunWords = 4 + 4 * kThreads * kRounds;
+
+__device__ __forceinline__ const uint32_t* load_prefix_runs(const uint16_t* __restrict__ row,
+                                                            int64_t nout, int64_t first, uint32_t* lds,
+                                                            uint32_t* round_tot, uint32_t* vmax) {
+    // first >= -1; the window of the first segment (first = -1) starts at 0
+    // with shift -1 (its sample -1 counts as 0)
+    const int64_t a = first < 0 ? 0 : first - (first & 3);
+    const int shift = static_cast<int>(first - a);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint16_t*>(row), 0, static_cast<int>(nout * 2), kRowRsrcWord3);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int off0 = static_cast<int>(a) * 2 + static_cast<int>(threadIdx.x) * 8;
+    uint32_t v[2 * kRounds];
+#pragma unroll
+    for (int i = 0; i < kRounds; ++i) {
+        const auto x = __builtin_amdgcn_raw_buffer_load_b64(rs, off0 + i * (8 * kThreads), 0, 0);
+        v[2 * i] = x[0];
+        v[2 * i + 1] = x[1];
+    }
+    uint32_t m = 0;
+    uint32_t excl[kRounds];
+#pragma unroll
+    for (int i = 0; i < kRounds; ++i) {
+        const uint32_t x0 = v[2 * i] & 0xFFFFu, x1 = v[2 * i] >> 16;
+        const uint32_t x2 = v[2 * i + 1] & 0xFFFFu, x3 = v[2 * i + 1] >> 16;
+        m = max(m, max(max(x0, x1), max(x2, x3)));
+        const uint32_t c = x0 + x1 + x2 + x3;
+        const uint32_t incl = wave_incl_scan(c);
+        excl[i] = incl - c;
+        if (lane == 63) round_tot[i * (kThreads / 64) + wave] = incl;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = max(m, static_cast<uint32_t>(__shfl_xor(m, o, 64)));
+    __syncthreads();
+    // after the barrier (ordered after the caller's clearing of *vmax) and
+    // before the final one (ordered before its readers)
+    if (lane == 0) atomicMax(vmax, m);
+    // the block's prefix before round i and wave w: every earlier round's
+    // four totals and this round's earlier waves
+    uint32_t base = 0;
+#pragma unroll
+    for (int i = 0; i < kRounds; ++i) {
+        const uint4 t = *reinterpret_cast<const uint4*>(round_tot + i * (kThreads / 64));
+        const uint32_t before = (wave > 0 ? t.x : 0u) + (wave > 1 ? t.y : 0u) + (wave > 2 ? t.z : 0u);
+        uint32_t run = base + before + excl[i];
+        base += t.x + t.y + t.z + t.w;
+        uint32_t w[4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            run += v[2 * i + h] & 0xFFFFu;
+            w[2 * h] = run;
+            run += v[2 * i + h] >> 16;
+            w[2 * h + 1] = run;
+        }
+        // lds[3 + k] = sum of s[a .. a + k): sample a + 4g + j ends at 4 + 4g + j
+        *reinterpret_cast<uint4*>(lds + 4 + 4 * (i * kThreads + threadIdx.x)) =
+            make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    if (threadIdx.x == 0) {
+        lds[2] = 0u;
+        lds[3] = 0u;
+    }
+    __syncthreads();
+    return lds + 3 + shift;
 }
 
 template <typename T>
@@ -336,8 +420,8 @@ constexpr int kPerThread = 32;
 // widths: positions outer, widths inner, every partial sum in registers, then
 // one block reduction through LDS (which the running sums no longer need).
 template <int NW>
-__device__ __forceinline__ void stats_full_nw(uint32_t* pl, const dd::Widths& W, uint64_t* s1_out,
-                                              u128* s2_out, uint32_t* mx_out) {
+__device__ __forceinline__ void stats_full_nw(const uint32_t* ps, uint32_t* pl, const dd::Widths& W,
+                                              uint64_t* s1_out, u128* s2_out, uint32_t* mx_out) {
     uint64_t s1[NW], s2[NW];
     uint32_t mx[NW];
     int woff[NW];
@@ -348,7 +432,7 @@ __device__ __forceinline__ void stats_full_nw(uint32_t* pl, const dd::Widths& W,
         s2[wi] = 0;
         woff[wi] = W.w[wi];
     }
-    const uint32_t* base = pl + 1 + threadIdx.x;
+    const uint32_t* base = ps + 1 + threadIdx.x;
 #pragma unroll 8
     for (int j = 0; j < kPerThread; ++j) {
         const uint32_t p0 = base[j * kThreads];
@@ -365,7 +449,7 @@ __device__ __forceinline__ void stats_full_nw(uint32_t* pl, const dd::Widths& W,
     // (After the main loop, so that its registers are free there.)
     constexpr int L = kPerThread * kThreads;
     for (int k = threadIdx.x + 1; k <= woff[NW - 1]; k += kThreads) {
-        const uint64_t dk = pl[L + k] - pl[k];
+        const uint64_t dk = ps[L + k] - ps[k];
 #pragma unroll
         for (int wi = 0; wi < NW; ++wi)
             if (k <= woff[wi]) s1[wi] += dk;
@@ -432,9 +516,10 @@ template <typename T, int NW>
 __global__ __launch_bounds__(kThreads) void boxcar_stats_kernel(const T* __restrict__ in,
                                                                 int64_t nout, int64_t nbx,
                                                                 dd::Widths W, int L, int nseg,
-                                                                dd::PeaksWs ws) {
-    extern __shared__ uint32_t pl[];
+                                                                int runs, dd::PeaksWs ws) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t pl[];
     __shared__ uint32_t wave_tot[kThreads / 64];
+    __shared__ __attribute__((aligned(16))) uint32_t round_tot[kRounds * (kThreads / 64)];
     __shared__ uint64_t red1[kThreads / 64][dd::kMaxWidths];
     __shared__ u128 red2[kThreads / 64][dd::kMaxWidths];
     __shared__ uint32_t redm[kThreads / 64][dd::kMaxWidths];
@@ -445,7 +530,16 @@ __global__ __launch_bounds__(kThreads) void boxcar_stats_kernel(const T* __restr
     const int w_max = W.w[W.n - 1];
     const int n = L + w_max + 1;
     if (threadIdx.x == 0) vmax = 0;
-    load_prefix(in + static_cast<int64_t>(d) * nout, nout, s0 - 1, n, pl, wave_tot, &vmax);
+    // the window's running sums: ps[i] - ps[j] = sum of s[s0 - 1 + j .. s0 - 1 + i)
+    const uint32_t* ps = pl;
+    if constexpr (std::is_same<T, uint16_t>::value) {
+        if (runs)
+            ps = load_prefix_runs(in + static_cast<int64_t>(d) * nout, nout, s0 - 1, pl, round_tot, &vmax);
+        else
+            load_prefix(in + static_cast<int64_t>(d) * nout, nout, s0 - 1, n, pl, wave_tot, &vmax);
+    } else {
+        load_prefix(in + static_cast<int64_t>(d) * nout, nout, s0 - 1, n, pl, wave_tot, &vmax);
+    }
     const int npos = static_cast<int>(min<int64_t>(L, nbx - s0));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t bmax = static_cast<uint64_t>(vmax) * static_cast<uint64_t>(w_max);
@@ -463,7 +557,7 @@ __global__ __launch_bounds__(kThreads) void boxcar_stats_kernel(const T* __restr
         __shared__ uint64_t f1[NWS];
         __shared__ u128 f2[NWS];
         __shared__ uint32_t fm[NWS];
-        stats_full_nw<NWS>(pl, W, f1, f2, fm);
+        stats_full_nw<NWS>(ps, pl, W, f1, f2, fm);
         __syncthreads();
         if (threadIdx.x < NW) {
             const int wi = threadIdx.x;
@@ -480,9 +574,9 @@ __global__ __launch_bounds__(kThreads) void boxcar_stats_kernel(const T* __restr
         u128 s2;
         uint32_t mx;
         if (small)
-            width_sums<true>(pl, npos, W.w[wi], &s1, &s2, &mx);
+            width_sums<true>(ps, npos, W.w[wi], &s1, &s2, &mx);
         else
-            width_sums<false>(pl, npos, W.w[wi], &s1, &s2, &mx);
+            width_sums<false>(ps, npos, W.w[wi], &s1, &s2, &mx);
         if (lane == 0) {
             red1[wave][wi] = s1;
             red2[wave][wi] = s2;
@@ -1095,11 +1189,17 @@ hipError_t launch_baseline(const void* in, int in_u16, int ndm, int64_t nout, in
 template <typename T, int NW>
 hipError_t launch_stats_t(const void* in, int64_t nout, const Widths& W, const PeaksLayout& lay,
                           const PeaksWs& ws, dim3 grid, size_t lds, hipStream_t s) {
+    // contiguous-run window loads (uint16 only): rows of a multiple of 4
+    // samples from an 8-byte aligned series, and a window that the runs cover
+    const int w_max = W.w[W.n - 1];
+    const int runs = std::is_same<T, uint16_t>::value && nout % 4 == 0 &&
+                     reinterpret_cast<uintptr_t>(in) % 8 == 0 && lay.L + w_max + 1 + 3 <= 4 * kThreads * kRounds;
+    if (runs) lds = std::max(lds, static_cast<size_t>(kRunWords) * 4);
     auto kern = boxcar_stats_kernel<T, NW>;
     hipError_t e = set_lds_limit(reinterpret_cast<const void*>(kern), lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, s, static_cast<const T*>(in), nout, lay.nbx,
-                       W, lay.L, lay.nseg, ws);
+                       W, lay.L, lay.nseg, runs, ws);
     return hipGetLastError();
 }
 

@@ -262,3 +262,28 @@ def test_find_peaks_wide_integer_paths(k):
     ev, (g1, g2, gt) = _find(series, widths, k, False)
     assert (g1 == s1).all() and (g2 == s2).all() and (gt == thr).all()
     events_equal(ev, ref)
+
+
+@pytest.mark.parametrize("nout", [3 * 8192 + 512, 3 * 8192 + 514, 8192 + 1024])
+def test_find_peaks_uint16_window_loads(nout):
+    """uint16 series whose rows are a multiple of 4 samples take the
+    statistics pass's 8-byte window loads (from sample 0 in a row's first
+    segment, whole 8192-position segments and a ragged last one); the other
+    row lengths take the per-sample loads.  Survey-level values, pulses that
+    cross segment edges, and one row of values near 2^16 (width-512 boxcars
+    just below 2^25, the largest the register fast path takes) -- all equal
+    the oracle."""
+    rng = np.random.default_rng(nout)
+    series = rng.integers(1400, 1700, size=(5, nout)).astype(np.int64)
+    series[1, 8150:8260] += 400            # across the first segment edge
+    series[2, :40] += 600                  # at the start of the row
+    series[3, nout - 30:] += 500           # at the end of the row
+    series[4, :] = rng.integers(60000, 65536, size=nout)
+    widths = [1 << i for i in range(10)]
+    bw = oracle.boxcar(series, widths)
+    ref = oracle.find_events(bw, 6.0)
+    s1, s2, thr = _ref_stats(bw, 6.0)
+    log("uint16 window loads nout", nout, "ref events", len(ref))
+    ev, (g1, g2, gt) = _find(series, widths, 6.0, True)
+    assert (g1 == s1).all() and (g2 == s2).all() and (gt == thr).all()
+    events_equal(ev, ref)
