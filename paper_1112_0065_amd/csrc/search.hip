@@ -416,6 +416,36 @@ __device__ __forceinline__ void width_sums(const uint32_t* pl, int npos, int w, 
 // Positions per thread in the fast path of a full segment.
 constexpr int kPerThread = 32;
 
+// Row stride of the per-width values in the fast path's block reductions
+// through LDS: the 16 lanes of one width read 16 consecutive values, and the
+// next width's lanes are 16 banks further on.
+constexpr int kRedStride = kThreads + 16;
+
+// Sum / maximum over the 16 lanes of a DPP row (every lane gets it): swaps
+// of neighbours and of pairs within each quad, then rotations by 4 and 8.
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x, int ctrl_sel) {
+    switch (ctrl_sel) {
+        case 0: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0xB1, 0xF, 0xF, false));
+        case 1: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x4E, 0xF, 0xF, false));
+        case 2: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x124, 0xF, 0xF, false));
+        default: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x128, 0xF, 0xF, false));
+    }
+}
+__device__ __forceinline__ uint64_t row_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const uint64_t o = (static_cast<uint64_t>(dpp_u32(static_cast<uint32_t>(v >> 32), c)) << 32) |
+                           dpp_u32(static_cast<uint32_t>(v), c);
+        v += o;
+    }
+    return v;
+}
+__device__ __forceinline__ uint32_t row_max_u32(uint32_t v) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v = max(v, dpp_u32(v, c));
+    return v;
+}
+
 // Fast path of a full segment with small values and NW (compile-time)
 // widths: positions outer, widths inner, every partial sum in registers, then
 // one block reduction through LDS (which the running sums no longer need).
@@ -455,60 +485,48 @@ __device__ __forceinline__ void stats_full_nw(const uint32_t* ps, uint32_t* pl, 
             if (k <= woff[wi]) s1[wi] += dk;
     }
     __syncthreads();   // the running sums are no longer needed: reuse pl
-    uint64_t* r = reinterpret_cast<uint64_t*>(pl);
+    // Per width, thread (wi, l) = 16 wi + l takes partials l, l+16, ..., of
+    // width wi (rows of kRedStride words: the next width's 16 lanes are 16
+    // banks further on), then the 16 lanes of the width, one DPP row, sum
+    // their values; lane 16 wi ends with width wi's total.
     const int t = threadIdx.x;
-    // squares: [NW][256] -> 16 partials per width -> 1
+    uint64_t* r = reinterpret_cast<uint64_t*>(pl);
 #pragma unroll
-    for (int wi = 0; wi < NW; ++wi) r[wi * kThreads + t] = s2[wi];
+    for (int wi = 0; wi < NW; ++wi) r[wi * kRedStride + t] = s2[wi];
     __syncthreads();
-    // thread (wi, l) sums partials l, l+16, ..., l+240 of width wi: the 16
-    // lanes of one width read 16 consecutive values (no bank conflicts)
     uint64_t acc = 0;
     if (t < NW * 16) {
-        const uint64_t* q = r + (t / 16) * kThreads + (t % 16);
+        const uint64_t* q = r + (t / 16) * kRedStride + (t % 16);
+#pragma unroll
         for (int k = 0; k < 16; ++k) acc += q[16 * k];
     }
-    __syncthreads();
-    if (t < NW * 16) r[t] = acc;
-    __syncthreads();
-    if (t < NW) {
-        uint64_t v = 0;
-        for (int k = 0; k < 16; ++k) v += r[t * 16 + k];
-        s2_out[t] = v;
-    }
+    acc = row_sum_u64(acc);
+    if (t < NW * 16 && (t & 15) == 0) s2_out[t >> 4] = acc;
     __syncthreads();
     // sums and maxima
+    uint32_t* rm = pl + 2 * NW * kRedStride;
 #pragma unroll
     for (int wi = 0; wi < NW; ++wi) {
-        r[wi * kThreads + t] = s1[wi];
-        pl[2 * NW * kThreads + wi * kThreads + t] = mx[wi];
+        r[wi * kRedStride + t] = s1[wi];
+        rm[wi * kRedStride + t] = mx[wi];
     }
     __syncthreads();
     uint64_t a1 = 0;
     uint32_t am = 0;
     if (t < NW * 16) {
-        const uint64_t* q = r + (t / 16) * kThreads + (t % 16);
-        const uint32_t* qm = pl + 2 * NW * kThreads + (t / 16) * kThreads + (t % 16);
+        const uint64_t* q = r + (t / 16) * kRedStride + (t % 16);
+        const uint32_t* qm = rm + (t / 16) * kRedStride + (t % 16);
+#pragma unroll
         for (int k = 0; k < 16; ++k) {
             a1 += q[16 * k];
             am = max(am, qm[16 * k]);
         }
     }
-    __syncthreads();
-    if (t < NW * 16) {
-        r[t] = a1;
-        pl[2 * NW * kThreads + t] = am;
-    }
-    __syncthreads();
-    if (t < NW) {
-        uint64_t v = 0;
-        uint32_t m = 0;
-        for (int k = 0; k < 16; ++k) {
-            v += r[t * 16 + k];
-            m = max(m, pl[2 * NW * kThreads + t * 16 + k]);
-        }
-        s1_out[t] = v;
-        mx_out[t] = m;
+    a1 = row_sum_u64(a1);
+    am = row_max_u32(am);
+    if (t < NW * 16 && (t & 15) == 0) {
+        s1_out[t >> 4] = a1;
+        mx_out[t >> 4] = am;
     }
 }
 
@@ -1207,10 +1225,10 @@ template <typename T>
 hipError_t launch_stats_w(const void* in, int64_t nout, const Widths& W, const PeaksLayout& lay,
                           const PeaksWs& ws, dim3 grid, size_t lds, hipStream_t s) {
     // the register fast path reuses the running-sum area (L + w_max + 1 words)
-    // for its reduction (3 * NW * 256 words)
+    // for its reduction (3 * NW * kRedStride words)
     const int w_max = W.w[W.n - 1];
     const int nw = (lay.L == kPerThread * kThreads && W.n <= 16 &&
-                    3 * W.n * kThreads <= lay.L + w_max + 1) ? W.n : 0;
+                    3 * W.n * kRedStride <= lay.L + w_max + 1) ? W.n : 0;
     switch (nw) {
 #define DD_NW(N) case N: return launch_stats_t<T, N>(in, nout, W, lay, ws, grid, lds, s);
         DD_NW(1) DD_NW(2) DD_NW(3) DD_NW(4) DD_NW(5) DD_NW(6) DD_NW(7) DD_NW(8)
