@@ -451,13 +451,12 @@ __device__ __forceinline__ uint32_t row_max_u32(uint32_t v) {
 // one block reduction through LDS (which the running sums no longer need).
 template <int NW>
 __device__ __forceinline__ void stats_full_nw(const uint32_t* ps, uint32_t* pl, const dd::Widths& W,
-                                              uint64_t* s1_out, u128* s2_out, uint32_t* mx_out) {
-    uint64_t s1[NW], s2[NW];
+                                              const dd::PeaksWs& ws, int64_t idx0, int64_t stride) {
+    uint64_t s2[NW];
     uint32_t mx[NW];
     int woff[NW];
 #pragma unroll
     for (int wi = 0; wi < NW; ++wi) {
-        s1[wi] = 0;
         mx[wi] = 0;
         s2[wi] = 0;
         woff[wi] = W.w[wi];
@@ -478,6 +477,9 @@ __device__ __forceinline__ void stats_full_nw(const uint32_t* ps, uint32_t* pl, 
     // each term a sum of L samples (below 2^32 by the caller's check).
     // (After the main loop, so that its registers are free there.)
     constexpr int L = kPerThread * kThreads;
+    uint64_t s1[NW];
+#pragma unroll
+    for (int wi = 0; wi < NW; ++wi) s1[wi] = 0;
     for (int k = threadIdx.x + 1; k <= woff[NW - 1]; k += kThreads) {
         const uint64_t dk = ps[L + k] - ps[k];
 #pragma unroll
@@ -501,7 +503,6 @@ __device__ __forceinline__ void stats_full_nw(const uint32_t* ps, uint32_t* pl, 
         for (int k = 0; k < 16; ++k) acc += q[16 * k];
     }
     acc = row_sum_u64(acc);
-    if (t < NW * 16 && (t & 15) == 0) s2_out[t >> 4] = acc;
     __syncthreads();
     // sums and maxima
     uint32_t* rm = pl + 2 * NW * kRedStride;
@@ -524,9 +525,14 @@ __device__ __forceinline__ void stats_full_nw(const uint32_t* ps, uint32_t* pl, 
     }
     a1 = row_sum_u64(a1);
     am = row_max_u32(am);
+    // every global write after the last barrier (a barrier would wait for
+    // them)
     if (t < NW * 16 && (t & 15) == 0) {
-        s1_out[t >> 4] = a1;
-        mx_out[t >> 4] = am;
+        const int64_t i = idx0 + (t >> 4) * stride;
+        ws.part_s2lo[i] = acc;
+        ws.part_s2hi[i] = 0u;   // below 2^63 (see the caller)
+        ws.part_s1[i] = a1;
+        ws.part_max[i] = am;
     }
 }
 
@@ -535,7 +541,10 @@ __global__ __launch_bounds__(kThreads) void boxcar_stats_kernel(const T* __restr
                                                                 int64_t nout, int64_t nbx,
                                                                 dd::Widths W, int L, int nseg,
                                                                 int runs, dd::PeaksWs ws) {
-    extern __shared__ __attribute__((aligned(16))) uint32_t pl[];
+    // the dynamic LDS as 16-byte elements, so that its base is 16-byte
+    // aligned (16-byte LDS accesses in the window loads)
+    extern __shared__ uint4 pl16[];
+    uint32_t* pl = reinterpret_cast<uint32_t*>(pl16);
     __shared__ uint32_t wave_tot[kThreads / 64];
     __shared__ __attribute__((aligned(16))) uint32_t round_tot[kRounds * (kThreads / 64)];
     __shared__ uint64_t red1[kThreads / 64][dd::kMaxWidths];
@@ -572,19 +581,9 @@ __global__ __launch_bounds__(kThreads) void boxcar_stats_kernel(const T* __restr
                       vmax < (1u << 19) && L == kPerThread * kThreads;
     constexpr int NWS = NW > 0 ? NW : 1;
     if (NW > 0 && full) {
-        __shared__ uint64_t f1[NWS];
-        __shared__ u128 f2[NWS];
-        __shared__ uint32_t fm[NWS];
-        stats_full_nw<NWS>(ps, pl, W, f1, f2, fm);
-        __syncthreads();
-        if (threadIdx.x < NW) {
-            const int wi = threadIdx.x;
-            const int64_t idx = (static_cast<int64_t>(wi) * gridDim.y + d) * nseg + seg;
-            ws.part_s1[idx] = f1[wi];
-            ws.part_s2lo[idx] = static_cast<uint64_t>(f2[wi]);
-            ws.part_s2hi[idx] = static_cast<uint64_t>(f2[wi] >> 64);
-            ws.part_max[idx] = fm[wi];
-        }
+        // partial of width wi at idx0 + wi * stride
+        stats_full_nw<NWS>(ps, pl, W, ws, static_cast<int64_t>(d) * nseg + seg,
+                           static_cast<int64_t>(gridDim.y) * nseg);
         return;
     }
     for (int wi = 0; wi < W.n; ++wi) {
