@@ -474,17 +474,32 @@ __device__ __forceinline__ void stats_full_nw(const uint32_t* ps, uint32_t* pl, 
     }
     // Sum of the segment's boxcars by telescoping: with P the running sums,
     //   sum_{j<L} (P[j+1+w] - P[j+1]) = sum_{k=1..w} (P[L+k] - P[k]),
-    // each term a sum of L samples (below 2^32 by the caller's check).
-    // (After the main loop, so that its registers are free there.)
+    // each term D(k) a sum of L samples (below 2^32 by the caller's check).
+    // (After the main loop, so that its registers are free there.)  Lane l
+    // of a wave takes k = k0 + l, 64 consecutive values, and a DPP scan of
+    // D's two 16-bit halves (each below 2^22 over 64 lanes) gives their
+    // inclusive prefix.  Lane wi < NW keeps width wi's sum: it takes the
+    // prefix at lane w - k0, clamped to 63 (every k of the wave when
+    // k0 + 63 <= w), and nothing when w < k0.
     constexpr int L = kPerThread * kThreads;
-    uint64_t s1[NW];
+    const int lane = threadIdx.x & 63;
+    int myw = 0;   // this lane's width (lanes >= NW: none)
 #pragma unroll
-    for (int wi = 0; wi < NW; ++wi) s1[wi] = 0;
-    for (int k = threadIdx.x + 1; k <= woff[NW - 1]; k += kThreads) {
-        const uint64_t dk = ps[L + k] - ps[k];
-#pragma unroll
-        for (int wi = 0; wi < NW; ++wi)
-            if (k <= woff[wi]) s1[wi] += dk;
+    for (int wi = 0; wi < NW; ++wi)
+        if (lane == wi) myw = woff[wi];
+    uint64_t s1 = 0;
+    for (int k0 = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) & ~63) + 1;
+         k0 <= woff[NW - 1]; k0 += kThreads) {
+        const int k = k0 + lane;
+        const int kc = min(k, woff[NW - 1]);   // k past the widest width reads in range, counts 0
+        const uint32_t dk = k <= woff[NW - 1] ? ps[L + kc] - ps[kc] : 0u;
+        const uint32_t lo = wave_incl_scan(dk & 0xFFFFu);
+        const uint32_t hi = wave_incl_scan(dk >> 16);
+        const int l = myw - k0;
+        const int src = min(max(l, 0), 63);
+        const uint32_t glo = static_cast<uint32_t>(__shfl(static_cast<int>(lo), src, 64));
+        const uint32_t ghi = static_cast<uint32_t>(__shfl(static_cast<int>(hi), src, 64));
+        if (l >= 0) s1 += static_cast<uint64_t>(glo) + (static_cast<uint64_t>(ghi) << 16);
     }
     __syncthreads();   // the running sums are no longer needed: reuse pl
     // Per width, thread (wi, l) = 16 wi + l takes partials l, l+16, ..., of
@@ -504,26 +519,23 @@ __device__ __forceinline__ void stats_full_nw(const uint32_t* ps, uint32_t* pl, 
     }
     acc = row_sum_u64(acc);
     __syncthreads();
-    // sums and maxima
+    // maxima, and the sums (one per wave and width)
     uint32_t* rm = pl + 2 * NW * kRedStride;
 #pragma unroll
-    for (int wi = 0; wi < NW; ++wi) {
-        r[wi * kRedStride + t] = s1[wi];
-        rm[wi * kRedStride + t] = mx[wi];
-    }
+    for (int wi = 0; wi < NW; ++wi) rm[wi * kRedStride + t] = mx[wi];
+    if (lane < NW) r[(t >> 6) * NW + lane] = s1;
     __syncthreads();
     uint64_t a1 = 0;
     uint32_t am = 0;
     if (t < NW * 16) {
-        const uint64_t* q = r + (t / 16) * kRedStride + (t % 16);
         const uint32_t* qm = rm + (t / 16) * kRedStride + (t % 16);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            a1 += q[16 * k];
-            am = max(am, qm[16 * k]);
+        for (int k = 0; k < 16; ++k) am = max(am, qm[16 * k]);
+        if ((t & 15) == 0) {
+#pragma unroll
+            for (int v = 0; v < kThreads / 64; ++v) a1 += r[v * NW + (t >> 4)];
         }
     }
-    a1 = row_sum_u64(a1);
     am = row_max_u32(am);
     // every global write after the last barrier (a barrier would wait for
     // them)
