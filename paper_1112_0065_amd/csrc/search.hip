@@ -225,15 +225,25 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     return x;
 }
 
+// Two uint16 values packed in a 32-bit word.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// c + the two 16-bit halves of v (one v_dot2_u32_u16 with the vector (1, 1)).
+__device__ __forceinline__ uint32_t add_halves(uint32_t v, uint32_t c) {
+    const u16x2 one = {1, 1};
+    return __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, v), one, c, false);
+}
+
 // The same running sums of a uint16 series window, for rows of a multiple of
 // 4 samples from an 8-byte aligned series, without the LDS passes of the
 // scan.  The window is read from a = first rounded down to a multiple of 4
 // (and not below 0) in kRounds rounds of 1024 samples; in round i thread t
 // takes samples a + 4(256 i + t) .. + 3 with one 8-byte load (every load lies
 // wholly inside the row or wholly past its end, where it reads 0).  The
-// thread sums its four, a DPP scan per round gives the wave's prefix, one
-// exchange of the wave totals of every round gives the block's, and each
-// group of four running sums goes to LDS with one 16-byte store.  The samples
+// thread sums its four (two packed 16-bit dot products), a DPP scan per
+// round gives the wave's prefix, one DPP scan of the 36 wave totals in
+// (round, wave) order gives the block's, and each group of four running
+// sums goes to LDS with one 16-byte store.  The samples
 // between a and first and past the window enter the sums too: only
 // differences of the running sums are used, and the largest value only gates
 // the fast path, so both stay exact.  lds needs kRunWords words.
@@ -250,7 +260,8 @@ __device__ __forceinline__ const uint32_t* load_prefix_runs(const uint16_t* __re
     const int shift = static_cast<int>(first - a);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint16_t*>(row), 0, static_cast<int>(nout * 2), kRowRsrcWord3);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int off0 = static_cast<int>(a) * 2 + static_cast<int>(threadIdx.x) * 8;
     uint32_t v[2 * kRounds];
 #pragma unroll
@@ -259,44 +270,41 @@ __device__ __forceinline__ const uint32_t* load_prefix_runs(const uint16_t* __re
         v[2 * i] = x[0];
         v[2 * i + 1] = x[1];
     }
-    uint32_t m = 0;
+    u16x2 m2 = {0, 0};
     uint32_t excl[kRounds];
 #pragma unroll
     for (int i = 0; i < kRounds; ++i) {
-        const uint32_t x0 = v[2 * i] & 0xFFFFu, x1 = v[2 * i] >> 16;
-        const uint32_t x2 = v[2 * i + 1] & 0xFFFFu, x3 = v[2 * i + 1] >> 16;
-        m = max(m, max(max(x0, x1), max(x2, x3)));
-        const uint32_t c = x0 + x1 + x2 + x3;
+        m2 = __builtin_elementwise_max(m2, __builtin_elementwise_max(__builtin_bit_cast(u16x2, v[2 * i]),
+                                                                     __builtin_bit_cast(u16x2, v[2 * i + 1])));
+        const uint32_t c = add_halves(v[2 * i + 1], add_halves(v[2 * i], 0u));
         const uint32_t incl = wave_incl_scan(c);
         excl[i] = incl - c;
         if (lane == 63) round_tot[i * (kThreads / 64) + wave] = incl;
     }
+    uint32_t m = max(static_cast<uint32_t>(m2.x), static_cast<uint32_t>(m2.y));
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) m = max(m, static_cast<uint32_t>(__shfl_xor(m, o, 64)));
     __syncthreads();
     // after the barrier (ordered after the caller's clearing of *vmax) and
     // before the final one (ordered before its readers)
     if (lane == 0) atomicMax(vmax, m);
-    // the block's prefix before round i and wave w: every earlier round's
-    // four totals and this round's earlier waves
-    uint32_t base = 0;
+    // The block's prefix before (round i, wave w) is the exclusive scan of
+    // the wave totals in (round, wave) order: lane 4 i + w of every wave
+    // scans them, and each wave reads its rounds' entries.
+    const uint32_t tv = lane < kRounds * (kThreads / 64) ? round_tot[lane] : 0u;
+    const uint32_t tin = wave_incl_scan(tv);
+    const uint32_t tex = tin - tv;
 #pragma unroll
     for (int i = 0; i < kRounds; ++i) {
-        const uint4 t = *reinterpret_cast<const uint4*>(round_tot + i * (kThreads / 64));
-        const uint32_t before = (wave > 0 ? t.x : 0u) + (wave > 1 ? t.y : 0u) + (wave > 2 ? t.z : 0u);
-        uint32_t run = base + before + excl[i];
-        base += t.x + t.y + t.z + t.w;
-        uint32_t w[4];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            run += v[2 * i + h] & 0xFFFFu;
-            w[2 * h] = run;
-            run += v[2 * i + h] >> 16;
-            w[2 * h + 1] = run;
-        }
+        const uint32_t pre = static_cast<uint32_t>(
+            __builtin_amdgcn_readlane(static_cast<int>(tex), i * (kThreads / 64) + wave));
+        const uint32_t run = pre + excl[i];
         // lds[3 + k] = sum of s[a .. a + k): sample a + 4g + j ends at 4 + 4g + j
-        *reinterpret_cast<uint4*>(lds + 4 + 4 * (i * kThreads + threadIdx.x)) =
-            make_uint4(w[0], w[1], w[2], w[3]);
+        const uint32_t w0 = run + (v[2 * i] & 0xFFFFu);
+        const uint32_t w1 = add_halves(v[2 * i], run);
+        const uint32_t w2 = w1 + (v[2 * i + 1] & 0xFFFFu);
+        const uint32_t w3 = add_halves(v[2 * i + 1], w1);
+        *reinterpret_cast<uint4*>(lds + 4 + 4 * (i * kThreads + threadIdx.x)) = make_uint4(w0, w1, w2, w3);
     }
     if (threadIdx.x == 0) {
         lds[2] = 0u;
