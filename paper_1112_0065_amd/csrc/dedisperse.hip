@@ -149,22 +149,23 @@ __device__ __forceinline__ void fill_stage(const dd::BeamArgs& a, cptr<int32_t> 
     for (int cl = wave; cl < cs; cl += kWaves) {
         const int c = c0 + cl;
         const int64_t w0 = w_base + (dlo_row[c] >> 5);
-        const int64_t avail = a.nwords - w0;   // > 0: w0 < nsamps / 32 + 1 < nwords
-        const int nq = static_cast<int>((avail < stride ? avail : stride) - 1);
+        // words of the row from w0 on: > 0 (w0 < nsamps / 32 + 1 < nwords) and
+        // below 2^31, so the bound is 32-bit scalar arithmetic (a 64-bit
+        // signed compare would go through vector registers)
+        const int avail = static_cast<int>(a.nwords - w0);
+        const int nq = min(avail, stride) - 1;
         // uniform source row; each lane adds its own 8-byte word offset
         const uint2* src = a.words + static_cast<int64_t>(c) * a.nwords + w0;
-        char* dst = lds + static_cast<int64_t>(cl) * a.pitch * 16;
-        for (int i = 0; i < nq; i += 64) {
-            // full batches of 64 quads need no per-lane check
-            const uint2* s = src + i;
-            char* q = dst + 16 * i;
-            if (i + 64 <= nq)
-                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(s + lane),
-                                                 (__attribute__((address_space(3))) void*)q, 16, 0, 0);
-            else if (lane < nq - i)
-                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(s + lane),
-                                                 (__attribute__((address_space(3))) void*)q, 16, 0, 0);
-        }
+        char* dst = lds + cl * a.pitch * 16;
+        // full batches of 64 quads need no per-lane check; only the last,
+        // partial one (if any) compares lanes
+        int i = 0;
+        for (; i + 64 <= nq; i += 64)
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + i + lane),
+                                             (__attribute__((address_space(3))) void*)(dst + 16 * i), 16, 0, 0);
+        if (i < nq && lane < nq - i)
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + i + lane),
+                                             (__attribute__((address_space(3))) void*)(dst + 16 * i), 16, 0, 0);
     }
 }
 
