@@ -146,18 +146,32 @@ __global__ __launch_bounds__(256) void repack_2bit_kernel(const uint8_t* __restr
             dst[1] = make_uint2(src[2], src[3]);
         }
     }
+    // The tiles cover the data words (nwords - 2 of them, an even number);
+    // when the last tile ends there, it also writes the two trailing zero
+    // words of its rows (no tile of its own for them).
+    const int64_t jz = (tile + 1) * kTileW;
+    if (tile == ntiles - 1 && jz < nwords) {   // then jz + 2 == nwords
+        for (int cl = tid; cl < kTileC; cl += 256) {
+            const int c = c0 + cl;
+            if (c >= nchans) continue;
+            uint2* dst = words + static_cast<int64_t>(c) * nwords + jz;
+            dst[0] = make_uint2(0u, 0u);
+            dst[1] = make_uint2(0u, 0u);
+        }
+    }
 }
 
 }  // namespace
 
 namespace dd {
 
-// Tiles cover the words, the two trailing ones included: every word of every
-// channel row is written once (zeros past the last sample).
+// Tiles cover the data words; the last one also writes the two trailing
+// words: every word of every channel row is written once (zeros past the
+// last sample).
 hipError_t launch_repack(const uint8_t* in, int64_t nsamps, int nchans, uint2* words,
                          int64_t nwords, hipStream_t s, const uint8_t* mask, int64_t mask_n) {
     if (nwords != repack_words(nsamps) || nwords % 2) return hipErrorInvalidValue;
-    const int64_t tiles_t = (nwords + kTileW - 1) / kTileW;
+    const int64_t tiles_t = (nwords - 2 + kTileW - 1) / kTileW;   // nwords - 2 >= 2 data words
     const int ncx = (nchans + kTileC - 1) / kTileC;
     const int64_t nblocks = tiles_t * ncx;    // one block per (tile, channel tile)
     if (nblocks > 0x7FFFFFFF) return hipErrorInvalidValue;
