@@ -223,3 +223,43 @@ def test_survey_config_whole_output_and_events():
         "events gpu", len(ev), "oracle", len(ref_ev))
     assert bad == [0, 0]
     events_equal(ev, ref_ev)
+
+
+def _planes_reference(x, nwords):
+    """The channel-major bit-plane copy by its definition: for channel c,
+    word j is a pair of 32-bit planes whose bit b is bit 0 (first) or bit 1
+    (second) of the level of sample 32j + b; samples past the input, the
+    two trailing words included, are zero."""
+    nchans, nsamps = x.shape
+    lv = np.zeros((nchans, 32 * nwords), dtype=np.uint8)
+    lv[:, :nsamps] = x
+    lo = np.packbits((lv & 1).astype(np.uint8), axis=1, bitorder="little").view("<u4")
+    hi = np.packbits((lv >> 1).astype(np.uint8), axis=1, bitorder="little").view("<u4")
+    return np.stack([lo, hi], axis=-1)   # [nchans][nwords][2]
+
+
+@pytest.mark.parametrize("nchans,nsamps", [(1024, 4096), (1024, 4096 + 64), (256, (1 << 15) + 37),
+                                           (1360, 1000), (4, 33), (2048, 512 * 3 + 511)])
+def test_repack_layout_every_word(nchans, nsamps):
+    """dedisp_repack writes every word of the bit-plane copy, and each equals
+    its definition from the oracle's unpacked levels.  The workspace is filled
+    with 0xAB first, so a word left unwritten fails.  The shapes cover whole
+    and partial 512-sample tiles (a row length of 2 ceil(nsamps / 64) + 2
+    words, whose two trailing words the last data tile writes when the data
+    words end on a tile boundary), partial channel tiles and a tiny beam."""
+    from paper_1112_0065_amd import _lib as L
+    torch = torch_dev()
+    rng = np.random.default_rng(nchans * 7 + nsamps)
+    packed = rng.integers(0, 256, size=nsamps * nchans // 4, dtype=np.uint8)
+    p = L.dedisp_plan_create(nchans, 1581.8, -400.0 / nchans, 64e-6, [0.0, 1.0])
+    nwords = 2 * ((nsamps + 63) // 64) + 2
+    nbytes = L.dedisp_workspace_bytes(p, nsamps)
+    assert nbytes >= nchans * nwords * 8
+    ws = torch.full((nbytes,), 0xAB, dtype=torch.uint8, device="cuda")
+    log("repack layout", nchans, nsamps)
+    L.dedisp_repack(p, to_dev(packed), nsamps, ws)
+    torch.cuda.synchronize()
+    got = ws[: nchans * nwords * 8].cpu().numpy().view("<u4").reshape(nchans, nwords, 2)
+    ref = _planes_reference(oracle.unpack_2bit(packed, nsamps, nchans), nwords)
+    bad = np.argwhere(got != ref)
+    assert len(bad) == 0, (len(bad), bad[:5].tolist())
