@@ -177,7 +177,10 @@ dedisp_status dedisp_execute_tile(dedisp_plan plan, const uint8_t* in_2bit, int6
  *   dedisp_repack: in_2bit (device, layout as dedisp_execute) -> workspace
  *     (device, >= dedisp_workspace_bytes(plan, nsamps), 256-byte aligned),
  *     the channel-major bit-plane copy: for channel c, word j holds samples
- *     32j..32j+31 as two 32-bit planes (bit 0 and bit 1 of each level).
+ *     32j..32j+31 as two 32-bit planes (bit 0 and bit 1 of each level; bit b
+ *     is sample 32j+b).  A channel's row is nwords = 2*ceil(nsamps/64) + 2
+ *     words of 8 bytes, at word c*nwords of the workspace; words past the
+ *     last sample, the two trailing ones included, are zero.
  *   dedisp_execute_repacked: dedispersion from that copy; `tile` (host) may
  *     be NULL for the default shape.
  * Errors and asynchrony as dedisp_execute. */
