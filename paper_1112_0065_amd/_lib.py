@@ -44,6 +44,13 @@ class DedispError(RuntimeError):
         self.status = status
 
 
+def _owned(obj) -> bool:
+    """Whether this process created the handle of `obj`.  A process forked
+    from one that uses the GPU (a multiprocessing pool) inherits the Python
+    objects; their destructors must not call into the library there."""
+    return getattr(obj, "_pid", None) == os.getpid()
+
+
 class _Tile(C.Structure):
     _fields_ = [("dms_per_block", C.c_int32), ("groups", C.c_int32), ("stage_chans", C.c_int32)]
 
@@ -246,14 +253,15 @@ class Plan:
 
     def __init__(self, handle: int, nchans: int, ndm: int, max_delay: int):
         self.handle = handle
+        self._pid = os.getpid()
         self.nchans = nchans
         self.ndm = ndm
         self.max_delay = max_delay
 
     def __del__(self):
-        if getattr(self, "handle", None) and _lib is not None:
+        if getattr(self, "handle", None) and _lib is not None and _owned(self):
             _lib.dedisp_plan_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     @property
     def _as_parameter_(self):
@@ -428,6 +436,7 @@ def events_from_buffer(buf, n: int) -> np.ndarray:
 class Subband:
     def __init__(self, handle: int, plan, nsub: int, group: int):
         self.handle = handle
+        self._pid = os.getpid()
         self.plan = plan            # keeps the fine-trial plan alive
         self.nsub = nsub
         self.group = group
@@ -437,9 +446,9 @@ class Subband:
         self.tile = (t.dms_per_block, t.groups, t.stage_chans)
 
     def close(self):
-        if getattr(self, "handle", None) and _lib is not None:
+        if getattr(self, "handle", None) and _lib is not None and _owned(self):
             _lib.dedisp_subband_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:
@@ -578,12 +587,13 @@ class Batch:
 
     def __init__(self, handle: int, plans):
         self.handle = handle
+        self._pid = os.getpid()
         self.plans = list(plans)
 
     def __del__(self):
-        if getattr(self, "handle", None) and _lib is not None:
+        if getattr(self, "handle", None) and _lib is not None and _owned(self):
             _lib.dedisp_batch_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
 
 def dedisp_batch_create(plans, widths, snr_thresh: float, out_u16: bool = True,
@@ -645,14 +655,16 @@ def dedisp_autotune(plan: Plan, nsamps: int, out_u16: bool = True,
 class Server:
     def __init__(self, handle: int, plans, model=None):
         self.handle = handle
+        self._pid = os.getpid()
         self.plans = list(plans)
         self.model = model
 
     def close(self):
-        if getattr(self, "handle", None) and _lib is not None:
+        if getattr(self, "handle", None) and _lib is not None and _owned(self):
             st = _lib.dedisp_serve_destroy(self.handle)
             self.handle = None
             _check(st)
+        self.handle = None
 
     def __del__(self):
         try:
@@ -758,11 +770,12 @@ def dedisp_serve_admission(budget: int, resident: int, slot_bytes: int) -> int:
 class Model:
     def __init__(self, handle: int):
         self.handle = handle
+        self._pid = os.getpid()
 
     def __del__(self):
-        if getattr(self, "handle", None) and _lib is not None:
+        if getattr(self, "handle", None) and _lib is not None and _owned(self):
             _lib.triage_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
 
 def triage_create(weights_path: Optional[str] = None, seed: int = 0) -> Model:

@@ -188,3 +188,19 @@ def test_bench_refuses_more_than_one_gpu():
                            env={**os.environ, **env})
         assert r.returncode == 2, (args, env, r.stderr)
         assert "exactly one GPU" in r.stderr and r.stdout == ""
+
+
+def test_handles_are_not_released_by_another_process():
+    """A process forked from one that owns library handles (a multiprocessing
+    pool) inherits their Python wrappers; when its garbage collector drops
+    them, the destructors must not call into the library (a bogus handle
+    here would crash the test if they did)."""
+    import gc
+    from paper_1112_0065_amd import _lib as L
+    L.lib()
+    objs = [L.Plan(0xDEAD0, 4, 1, 0), L.Model(0xDEAD1), L.Batch(0xDEAD2, []), L.Server(0xDEAD3, [])]
+    for o in objs:
+        o._pid = -1            # as if created by the parent of a fork
+    del o
+    objs.clear()
+    gc.collect()
