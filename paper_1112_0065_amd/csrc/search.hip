@@ -424,9 +424,10 @@ __device__ __forceinline__ void width_sums(const uint32_t* pl, int npos, int w, 
 // Positions per thread in the fast path of a full segment.
 constexpr int kPerThread = 32;
 
-// Row stride of the per-width values in the fast path's block reductions
-// through LDS: the 16 lanes of one width read 16 consecutive values, and the
-// next width's lanes are 16 banks further on.
+// Row stride, in values, of the per-width rows in the fast path's block
+// reductions through LDS: the 16 lanes of one width read 16 consecutive
+// values, and the next width's lanes start 16 banks further on for 4-byte
+// values (32 for 8-byte ones).
 constexpr int kRedStride = kThreads + 16;
 
 // Sum / maximum over the 16 lanes of a DPP row (every lane gets it): swaps
@@ -511,8 +512,8 @@ __device__ __forceinline__ void stats_full_nw(const uint32_t* ps, uint32_t* pl, 
     }
     __syncthreads();   // the running sums are no longer needed: reuse pl
     // Per width, thread (wi, l) = 16 wi + l takes partials l, l+16, ..., of
-    // width wi (rows of kRedStride words: the next width's 16 lanes are 16
-    // banks further on), then the 16 lanes of the width, one DPP row, sum
+    // width wi (rows of kRedStride values: the next width's 16 lanes start
+    // on other banks), then the 16 lanes of the width, one DPP row, sum
     // their values; lane 16 wi ends with width wi's total.
     const int t = threadIdx.x;
     uint64_t* r = reinterpret_cast<uint64_t*>(pl);
